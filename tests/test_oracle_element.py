@@ -1,0 +1,385 @@
+"""Pins of the oracle's element and global assembly (Sec. 4.1 precompute;
+Sec. 4.3, Eqs. F_assembly, fint_local, fint_global; Sec. 4.4.2,
+Eq. tangent_block) against invariants, closed forms and independent routines.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2604_10357_amd import workloads as W
+
+
+def small_t10(nx=2, ny=2, nz=2, L=(0.3, 0.2, 0.25)):
+    return W.kuhn_t10_box(nx, ny, nz, *L)
+
+
+def perturbed(mesh, rng, scale):
+    return (mesh.X + rng.uniform(-1, 1, mesh.X.shape) * scale).ravel()
+
+
+MR_KV = dict(kind=2, params=(2e5, 5e4, 1e8), eta=1e3, lam_v=1e3)
+SVK_KV = dict(kind=1, params=(1e7, 0.3), eta=2e3, lam_v=1e3)
+
+
+def mat(orc, d, kv=True):
+    return orc.material(d["kind"], d["params"], d["eta"] if kv else 0.0, d["lam_v"] if kv else 0.0)
+
+
+def dense_from_csr(row_off, cols, vals, n):
+    K = np.zeros((n, n))
+    for r in range(n):
+        K[r, cols[row_off[r]:row_off[r + 1]]] += vals[row_off[r]:row_off[r + 1]]
+    return K
+
+
+# ------------------------------------------------------------------ geometry
+
+def test_quadrature_volume_and_identity(orc):
+    rng = np.random.default_rng(20)
+    mesh = small_t10()
+    X = mesh.X + rng.uniform(-0.01, 0.01, mesh.X.shape)  # still positively oriented
+    # keep mid-edge nodes at midpoints (straight tetrahedra)
+    for k, (a, b) in enumerate(W.T10_EDGES):
+        X[mesh.conn[:, 4 + k]] = 0.5 * (X[mesh.conn[:, a]] + X[mesh.conn[:, b]])
+    m = orc.Mesh(orc.T10, X, mesh.conn)
+    total = 0.0
+    for e in range(m.n_elem):
+        dV, g = orc.element_geometry(m, e)
+        c = mesh.conn[e]
+        vol = np.linalg.det(np.stack([X[c[1]] - X[c[0]], X[c[2]] - X[c[0]], X[c[3]] - X[c[0]]])) / 6
+        assert abs(dV.sum() - vol) <= 1e-14 * abs(vol) * 10
+        for qp in range(5):
+            ident = X[c].T @ g[qp]
+            assert np.abs(ident - np.eye(3)).max() < 1e-12
+        total += dV.sum()
+    assert abs(total - 0.3 * 0.2 * 0.25) < 0.02 * 0.015  # perturbed box, roughly its volume
+
+
+def test_shell_volume(orc):
+    mesh = W.ancf3443_plate(3, 2, 0.6, 0.3, 0.01)  # 0.2 x 0.15 elements
+    m = orc.Mesh.of(mesh)
+    for e in range(m.n_elem):
+        dV, g = orc.element_geometry(m, e)
+        assert abs(dV.sum() - 0.2 * 0.15 * 0.01) < 1e-17
+        coefs = mesh.X[4 * mesh.conn[e][:, None] + np.arange(4)[None, :]].reshape(16, 3)
+        for qp in range(dV.shape[0]):
+            assert np.abs(coefs.T @ g[qp] - np.eye(3)).max() < 1e-12
+
+
+# ------------------------------------------------------------------ invariants
+
+def t10_workload(orc, kv=True, material=MR_KV, seed=21):
+    rng = np.random.default_rng(seed)
+    mesh = small_t10()
+    q = perturbed(mesh, rng, 0.004)
+    qdot = rng.normal(0, 0.05, q.shape)
+    return orc.Mesh.of(mesh), mat(orc, material, kv), q, qdot
+
+
+@pytest.mark.parametrize("material", [MR_KV, SVK_KV])
+def test_reference_configuration_zero_force(orc, material):
+    m, mt, q, qdot = t10_workload(orc, True, material)
+    f, _ = orc.assemble(m, mt, m.X.ravel().copy(), np.zeros_like(q), want_K=False)
+    assert np.abs(f).max() == 0.0
+
+
+@pytest.mark.parametrize("material", [MR_KV, SVK_KV])
+def test_rigid_motion_zero_force_t10(orc, material):
+    m, mt, q, qdot = t10_workload(orc, True, material)
+    R = W.rotation_matrix([1.0, -2.0, 0.5], 0.7)
+    t = np.array([0.3, -1.0, 2.0])
+    x = m.X @ R.T + t
+    omega = np.array([0.4, -0.2, 1.1])
+    c = x.mean(axis=0)
+    v = np.cross(omega, x - c) + np.array([0.1, 0.2, -0.3])
+    f, _ = orc.assemble(m, mt, x.ravel().copy(), v.ravel().copy(), want_K=False)
+    # scale: force produced by a 1e-3 strain
+    f_ref, _ = orc.assemble(m, mt, (m.X * 1.001).ravel().copy(), None, want_K=False)
+    assert np.abs(f).max() <= 1e-9 * np.abs(f_ref).max()
+
+
+def test_rigid_motion_zero_force_shell(orc):
+    mesh = W.ancf3443_plate(3, 3, 0.6, 0.6, 0.02)
+    m = orc.Mesh.of(mesh)
+    mt = orc.material(orc.SVK, (2e9, 0.3), 5e3, 5e3)
+    R = W.rotation_matrix([0.3, 1.0, -0.4], 1.1)
+    X = mesh.X.copy()
+    x = X @ R.T  # rotates positions and gradient vectors alike
+    x[0::4] += np.array([0.5, -0.2, 0.9])  # translation acts on positions only
+    omega = np.array([-0.3, 0.5, 0.8])
+    v = np.cross(omega, x)  # d/dt of R(t) applied to every coefficient vector
+    v[0::4] += np.array([0.2, 0.0, -0.1])
+    f, _ = orc.assemble(m, mt, x.ravel().copy(), v.ravel().copy(), want_K=False)
+    x2 = X.copy()
+    x2[0::4] *= 1.001
+    f_ref, _ = orc.assemble(m, mt, x2.ravel().copy(), None, want_K=False)
+    assert np.abs(f).max() <= 1e-8 * np.abs(f_ref).max()
+
+
+@pytest.mark.parametrize("material", [MR_KV, SVK_KV])
+def test_momentum_balance(orc, material):
+    m, mt, q, qdot = t10_workload(orc, True, material)
+    f, _ = orc.assemble(m, mt, q, qdot, want_K=False)
+    fv = f.reshape(-1, 3)
+    x = q.reshape(-1, 3)
+    scale = np.abs(fv).max()
+    assert np.abs(fv.sum(axis=0)).max() <= 1e-12 * scale * len(fv)
+    assert np.abs(np.cross(x, fv).sum(axis=0)).max() <= 1e-12 * scale * len(fv)
+
+
+def boundary_faces(conn):
+    faces = {}
+    for e, c in enumerate(conn):
+        for tri in ((0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)):
+            key = tuple(sorted(c[list(tri)]))
+            faces.setdefault(key, []).append(e)
+    return [k for k, v in faces.items() if len(v) == 1]
+
+
+@pytest.mark.parametrize("material", [MR_KV, SVK_KV])
+def test_t10_patch_test(orc, material):
+    """Affine motion => constant P.  By the divergence theorem the nodal force
+    is the boundary integral of P n N_a; on a 6-node triangle the vertex
+    functions integrate to zero and the edge functions to area/3, so vertex
+    forces vanish exactly and each boundary edge node gets the sum over its
+    faces of (area/3) P n."""
+    mesh = small_t10()
+    m = orc.Mesh.of(mesh)
+    mt = mat(orc, material, kv=False)
+    A = np.eye(3) + np.array([[0.02, -0.01, 0.005], [0.004, -0.015, 0.01], [0.0, 0.008, 0.012]])
+    t = np.array([0.1, 0.2, -0.05])
+    x = mesh.X @ A.T + t
+    f, _ = orc.assemble(m, mt, x.ravel().copy(), None, want_K=False)
+    P = orc.pk1(mt, A - np.eye(3))
+    fv = f.reshape(-1, 3)
+    expect = np.zeros_like(fv)
+    edge_of = {}
+    for c in mesh.conn:
+        for k, (a, b) in enumerate(W.T10_EDGES):
+            edge_of[tuple(sorted((c[a], c[b])))] = c[4 + k]
+    centroid = mesh.X.mean(axis=0)
+    for tri in boundary_faces(mesh.conn):
+        p0, p1, p2 = mesh.X[list(tri)]
+        nrm = np.cross(p1 - p0, p2 - p0)
+        area = 0.5 * np.linalg.norm(nrm)
+        n = nrm / np.linalg.norm(nrm)
+        if np.dot(n, p0 - centroid) < 0:
+            n = -n
+        for a, b in itertools.combinations(tri, 2):
+            expect[edge_of[tuple(sorted((a, b)))]] += area / 3 * (P @ n)
+    scale = np.abs(expect).max()
+    assert np.abs(fv - expect).max() <= 1e-11 * scale
+    vertices = np.unique(mesh.conn[:, :4])
+    assert np.abs(fv[vertices]).max() <= 1e-11 * scale
+
+
+def test_shell_patch_test_interior_nodes(orc):
+    """Affine field on the flat plate: constant F and P.  For the r, r_x, r_y
+    coefficients of an interior node the patch integral of P grad S cancels
+    (the in-plane functions vanish with their tangential slopes on the patch
+    boundary).  For r_z the shape function is z b_p with grad = z grad b_p +
+    b_p e_Z: the first term integrates to zero through the thickness and the
+    second leaves the thickness resultant H * (sum of element areas / 4) * P e_Z
+    = H lx ly P e_Z."""
+    mesh = W.ancf3443_plate(4, 4, 1.0, 1.0, 0.02)
+    m = orc.Mesh.of(mesh)
+    mt = orc.material(orc.SVK, (2e9, 0.3))
+    A = np.eye(3) + np.array([[0.01, 0.004, 0.0], [-0.003, 0.02, 0.0], [0.002, -0.001, 0.015]])
+    x = mesh.X.copy()
+    x[0::4] = mesh.X[0::4] @ A.T
+    x[1::4] = A[:, 0]
+    x[2::4] = A[:, 1]
+    x[3::4] = A[:, 2]
+    f, _ = orc.assemble(m, mt, x.ravel().copy(), None, want_K=False)
+    fv = f.reshape(-1, 4, 3)
+    pos = mesh.X[0::4]
+    interior = np.where((pos[:, 0] > 1e-9) & (pos[:, 0] < 1 - 1e-9) & (pos[:, 1] > 1e-9) & (pos[:, 1] < 1 - 1e-9))[0]
+    assert len(interior) == 9
+    scale = np.abs(fv).max()
+    assert np.abs(fv[interior, :3]).max() <= 1e-11 * scale
+    P = orc.pk1(mt, A - np.eye(3))
+    expect_rz = 0.02 * 0.25 * 0.25 * P[:, 2]
+    assert np.abs(fv[interior, 3] - expect_rz[None, :]).max() <= 1e-11 * scale
+
+
+# ------------------------------------------------------------------ tangent
+
+def test_undamped_tangent_symmetric(orc):
+    for material in (MR_KV, SVK_KV):
+        m, mt, q, qdot = t10_workload(orc, False, material)
+        ro, cols = orc.csr_pattern(m)
+        _, vals = orc.assemble(m, mt, q, None, 1.0, 0.0, pattern=(ro, cols), want_f=False)
+        K = dense_from_csr(ro, cols, vals, m.n_dof)
+        assert np.abs(K - K.T).max() <= 1e-12 * np.abs(K).max()
+
+
+@pytest.mark.parametrize("material", [MR_KV, SVK_KV])
+def test_tangent_matches_central_differences(orc, material):
+    m, mt, q, qdot = t10_workload(orc, True, material, seed=22)
+    ro, cols = orc.csr_pattern(m)
+    rng = np.random.default_rng(23)
+    v = rng.normal(size=q.shape)
+    eps = 1e-6 * 0.01  # absolute step on positions, well inside the element size
+    _, Kq = orc.assemble(m, mt, q, qdot, 1.0, 0.0, pattern=(ro, cols), want_f=False)
+    _, Kv = orc.assemble(m, mt, q, qdot, 0.0, 1.0, pattern=(ro, cols), want_f=False)
+    Kq = dense_from_csr(ro, cols, Kq, m.n_dof)
+    Kv = dense_from_csr(ro, cols, Kv, m.n_dof)
+    fp, _ = orc.assemble(m, mt, q + eps * v, qdot, want_K=False)
+    fm, _ = orc.assemble(m, mt, q - eps * v, qdot, want_K=False)
+    fd = (fp - fm) / (2 * eps)
+    assert np.abs(Kq @ v - fd).max() <= 1e-7 * np.abs(fd).max()
+    epsv = 1e-3
+    fp, _ = orc.assemble(m, mt, q, qdot + epsv * v, want_K=False)
+    fm, _ = orc.assemble(m, mt, q, qdot - epsv * v, want_K=False)
+    fd = (fp - fm) / (2 * epsv)
+    assert np.abs(Kv @ v - fd).max() <= 1e-9 * np.abs(fd).max()
+    # (alpha, beta) = (h, 1) is the velocity-level Jacobian of f(q_n + h v, v)
+    h = 1e-3
+    _, Kh = orc.assemble(m, mt, q, qdot, h, 1.0, pattern=(ro, cols), want_f=False)
+    Kh = dense_from_csr(ro, cols, Kh, m.n_dof)
+    assert np.abs(Kh - (h * Kq + Kv)).max() <= 1e-12 * np.abs(Kh).max()
+
+
+def test_shell_tangent_matches_central_differences(orc):
+    wl = W.shell_plate(3, 31, "small", thickness=0.02)
+    m = orc.Mesh.of(wl.mesh)
+    mt = orc.material(orc.SVK, (2e9, 0.3), 1e4, 1e4)
+    rng = np.random.default_rng(32)
+    qdot = rng.normal(0, 0.05, wl.q.shape)
+    ro, cols = orc.csr_pattern(m)
+    _, Kq = orc.assemble(m, mt, wl.q, qdot, 1.0, 0.0, pattern=(ro, cols), want_f=False)
+    Kq = dense_from_csr(ro, cols, Kq, m.n_dof)
+    v = rng.normal(size=wl.q.shape)
+    eps = 1e-7
+    fp, _ = orc.assemble(m, mt, wl.q + eps * v, qdot, want_K=False)
+    fm, _ = orc.assemble(m, mt, wl.q - eps * v, qdot, want_K=False)
+    fd = (fp - fm) / (2 * eps)
+    assert np.abs(Kq @ v - fd).max() <= 1e-6 * np.abs(fd).max()
+
+
+@pytest.mark.parametrize("material", [MR_KV, SVK_KV])
+def test_single_element_rigid_modes(orc, material):
+    # an unconstrained element at rest has exactly 6 zero-energy modes
+    X = np.array([[0, 0, 0], [0.1, 0, 0], [0, 0.12, 0], [0.01, 0.02, 0.09]], dtype=float)
+    X = np.vstack([X, [(X[a] + X[b]) / 2 for a, b in W.T10_EDGES]])
+    m = orc.Mesh(orc.T10, X, np.arange(10, dtype=np.int32)[None, :])
+    mt = mat(orc, material, kv=False)
+    _, K = orc.element(m, mt, 0, X.ravel().copy(), None, 1.0, 0.0)
+    ev = np.linalg.eigvalsh(0.5 * (K + K.T))
+    tol = 1e-10 * ev.max()
+    assert np.sum(np.abs(ev) < tol) == 6
+    assert ev.min() > -tol
+
+
+def t10_bmatrix_stiffness(Xe, lam, mu):
+    """Independent small-strain stiffness of a straight T10 element: Voigt
+    B-matrix, barycentric gradients from the corner positions and the
+    degree-2 4-point tetrahedron rule (exact for the quadratic integrand)."""
+    M = np.vstack([np.ones(4), Xe[:4].T])          # 4x4: [1; x; y; z] per corner
+    Minv = np.linalg.inv(M)                        # L = Minv @ [1, x, y, z]
+    gradL = Minv[:, 1:]                            # (4, 3) constant gradients
+    vol = abs(np.linalg.det(np.stack([Xe[1] - Xe[0], Xe[2] - Xe[0], Xe[3] - Xe[0]]))) / 6
+    a = (5 + 3 * np.sqrt(5)) / 20
+    b = (5 - np.sqrt(5)) / 20
+    pts = [np.full(4, b) for _ in range(4)]
+    for i in range(4):
+        pts[i][i] = a
+    D = np.zeros((6, 6))
+    D[:3, :3] = lam
+    D[:3, :3] += 2 * mu * np.eye(3)
+    D[3:, 3:] = mu * np.eye(3)
+    K = np.zeros((30, 30))
+    for L in pts:
+        grads = [(4 * L[c] - 1) * gradL[c] for c in range(4)]
+        grads += [4 * (L[c] * gradL[d] + L[d] * gradL[c]) for c, d in W.T10_EDGES]
+        B = np.zeros((6, 30))
+        for n, g in enumerate(grads):
+            B[0, 3 * n] = g[0]
+            B[1, 3 * n + 1] = g[1]
+            B[2, 3 * n + 2] = g[2]
+            B[3, 3 * n + 1], B[3, 3 * n + 2] = g[2], g[1]
+            B[4, 3 * n], B[4, 3 * n + 2] = g[2], g[0]
+            B[5, 3 * n], B[5, 3 * n + 1] = g[1], g[0]
+        K += B.T @ D @ B * vol / 4
+    return K
+
+
+def test_small_strain_stiffness_matches_bmatrix(orc):
+    rng = np.random.default_rng(24)
+    X = np.array([[0, 0, 0], [0.1, 0.01, 0], [0.02, 0.12, 0.01], [0.01, 0.02, 0.09]], dtype=float)
+    X += rng.uniform(-0.005, 0.005, X.shape)
+    X = np.vstack([X, [(X[a] + X[b]) / 2 for a, b in W.T10_EDGES]])
+    m = orc.Mesh(orc.T10, X, np.arange(10, dtype=np.int32)[None, :])
+    E, nu = 1e7, 0.3
+    lam, mu = E * nu / ((1 + nu) * (1 - 2 * nu)), E / (2 * (1 + nu))
+    _, K = orc.element(m, orc.material(orc.SVK, (E, nu)), 0, X.ravel().copy(), None, 1.0, 0.0)
+    Kb = t10_bmatrix_stiffness(X, lam, mu)
+    assert np.abs(K - Kb).max() <= 1e-12 * np.abs(Kb).max()
+    # Mooney-Rivlin linearises to shear 2(mu10+mu01), bulk kappa
+    mu10, mu01, kap = 2e5, 5e4, 1e8
+    G = 2 * (mu10 + mu01)
+    _, K = orc.element(m, orc.material(orc.MR, (mu10, mu01, kap)), 0, X.ravel().copy(), None, 1.0, 0.0)
+    Kb = t10_bmatrix_stiffness(X, kap - 2 * G / 3, G)
+    assert np.abs(K - Kb).max() <= 1e-12 * np.abs(Kb).max()
+    # viscous Jacobian at rest: Newtonian "Lame" constants (lam_v, eta)
+    eta, lv = 1e3, 7e2
+    _, K = orc.element(m, orc.material(orc.MR, (mu10, mu01, kap), eta, lv), 0, X.ravel().copy(),
+                       np.zeros(30), 0.0, 1.0)
+    Kb = t10_bmatrix_stiffness(X, lv, eta)
+    assert np.abs(K - Kb).max() <= 1e-12 * np.abs(Kb).max()
+
+
+def test_force_is_energy_gradient(orc):
+    for material in (MR_KV, SVK_KV):
+        m, mt, q, _ = t10_workload(orc, False, material, seed=25)
+        rng = np.random.default_rng(26)
+        v = rng.normal(size=q.shape)
+        f, _ = orc.assemble(m, mt, q, None, want_K=False)
+        eps = 1e-7
+        dE = (orc.energy(m, mt, q + eps * v) - orc.energy(m, mt, q - eps * v)) / (2 * eps)
+        assert abs(f @ v - dE) <= 1e-6 * abs(dE)
+
+
+def test_force_linear_in_parameters(orc):
+    m, _, q, qdot = t10_workload(orc)
+    a = orc.material(orc.MR, (2e5, 0.0, 0.0), 1e3, 0.0)
+    b = orc.material(orc.MR, (0.0, 5e4, 1e8), 0.0, 7e2)
+    ab = orc.material(orc.MR, (2e5, 5e4, 1e8), 1e3, 7e2)
+    fa, _ = orc.assemble(m, a, q, qdot, want_K=False)
+    fb, _ = orc.assemble(m, b, q, qdot, want_K=False)
+    fab, _ = orc.assemble(m, ab, q, qdot, want_K=False)
+    assert np.abs(fa + fb - fab).max() <= 1e-12 * np.abs(fab).max()
+
+
+# ------------------------------------------------------------------ VJP
+
+@pytest.mark.parametrize("material", [MR_KV, SVK_KV])
+def test_vjp(orc, material):
+    m, mt, q, qdot = t10_workload(orc, True, material, seed=27)
+    rng = np.random.default_rng(28)
+    w = rng.normal(size=q.shape)
+    gq, gqd, gp = orc.vjp(m, mt, q, qdot, w)
+    ro, cols = orc.csr_pattern(m)
+    _, Kq = orc.assemble(m, mt, q, qdot, 1.0, 0.0, pattern=(ro, cols), want_f=False)
+    _, Kv = orc.assemble(m, mt, q, qdot, 0.0, 1.0, pattern=(ro, cols), want_f=False)
+    Kq = dense_from_csr(ro, cols, Kq, m.n_dof)
+    Kv = dense_from_csr(ro, cols, Kv, m.n_dof)
+    assert np.abs(gq - Kq.T @ w).max() <= 1e-12 * np.abs(gq).max()
+    assert np.abs(gqd - Kv.T @ w).max() <= 1e-12 * np.abs(gqd).max()
+    # parameter gradient against central differences (relative step 1e-6)
+    params = list(material["params"]) + [0.0] * (3 - len(material["params"]))
+    base = params + [material["eta"], material["lam_v"]]
+    for i in range(5):
+        if base[i] == 0.0:
+            continue
+        h = 1e-6 * base[i]
+        up, dn = list(base), list(base)
+        up[i] += h
+        dn[i] -= h
+        mu_ = orc.material(material["kind"], up[:3], up[3], up[4])
+        md_ = orc.material(material["kind"], dn[:3], dn[3], dn[4])
+        fu, _ = orc.assemble(m, mu_, q, qdot, want_K=False)
+        fdn, _ = orc.assemble(m, md_, q, qdot, want_K=False)
+        fd = w @ (fu - fdn) / (2 * h)
+        assert abs(gp[i] - fd) <= 1e-6 * abs(fd), (i, gp[i], fd)

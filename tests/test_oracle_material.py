@@ -1,0 +1,179 @@
+"""Pins of the oracle's constitutive law (Sec. 4.3, Stage 1: P = P_el + P_vis;
+Sec. 4.4.2: the material tangent A = dP/dF).
+
+The paper defers the SVK / Mooney-Rivlin / Kelvin-Voigt formulas to Part I, so
+the oracle takes textbook readings.  These tests tie them to facts that do not
+depend on how the oracle writes them: P is the derivative of the energy,
+A is the derivative of P, textbook small-strain limits (Hooke's law with
+Lame constants from E and nu; shear 2(mu10+mu01) and bulk kappa for
+Mooney-Rivlin), closed-form energies of special deformations, objectivity,
+and the Newtonian-fluid limit of the viscous stress.
+"""
+import numpy as np
+import pytest
+
+SVK_P = (7e8, 0.33)
+MR_P = (7.89e7, 5.26e7, 1.03e9)
+
+
+def rand_hd(rng, scale):
+    return rng.normal(size=(3, 3)) * scale
+
+
+def mats(orc, kv=False):
+    eta, lv = (3e5, 2e5) if kv else (0.0, 0.0)
+    return {"svk": orc.material(orc.SVK, SVK_P, eta, lv), "mr": orc.material(orc.MR, MR_P, eta, lv)}
+
+
+@pytest.mark.parametrize("name", ["svk", "mr"])
+def test_pk1_is_energy_gradient(orc, name):
+    m = mats(orc)[name]
+    rng = np.random.default_rng(10)
+    for _ in range(5):
+        Hd = rand_hd(rng, 0.1)
+        P = orc.pk1(m, Hd)
+        eps = 1e-6
+        fd = np.zeros((3, 3))
+        for i in range(3):
+            for j in range(3):
+                e = np.zeros((3, 3))
+                e[i, j] = eps
+                fd[i, j] = (orc.energy_density(m, Hd + e) - orc.energy_density(m, Hd - e)) / (2 * eps)
+        assert np.abs(P - fd).max() <= 2e-7 * np.abs(P).max()
+
+
+@pytest.mark.parametrize("name", ["svk", "mr"])
+@pytest.mark.parametrize("kv", [False, True])
+def test_tangent_is_stress_derivative(orc, name, kv):
+    m = mats(orc, kv)[name]
+    rng = np.random.default_rng(11)
+    for _ in range(4):
+        Hd = rand_hd(rng, 0.1)
+        Fd = rng.normal(size=(3, 3))
+        A = orc.tangent(m, Hd, Fd, 1.0, 0.0)
+        B = orc.tangent(m, Hd, Fd, 0.0, 1.0)
+        eps = 1e-6
+        for k in range(3):
+            for L in range(3):
+                e = np.zeros((3, 3))
+                e[k, L] = eps
+                dPdF = (orc.pk1(m, Hd + e, Fd) - orc.pk1(m, Hd - e, Fd)) / (2 * eps)
+                dPdFd = (orc.pk1(m, Hd, Fd + e) - orc.pk1(m, Hd, Fd - e)) / (2 * eps)
+                scale = np.abs(A).max()
+                assert np.abs(A[:, :, k, L] - dPdF).max() <= 1e-7 * scale
+                assert np.abs(B[:, :, k, L] - dPdFd).max() <= 1e-7 * max(np.abs(B).max(), 1.0)
+        # linear combination
+        C = orc.tangent(m, Hd, Fd, 0.3, -2.0)
+        assert np.abs(C - (0.3 * A - 2.0 * B)).max() <= 1e-12 * np.abs(C).max()
+
+
+@pytest.mark.parametrize("name", ["svk", "mr"])
+def test_hyperelastic_tangent_major_symmetry(orc, name):
+    m = mats(orc)[name]
+    rng = np.random.default_rng(12)
+    Hd = rand_hd(rng, 0.2)
+    A = orc.tangent(m, Hd, None, 1.0, 0.0)
+    assert np.abs(A - A.transpose(2, 3, 0, 1)).max() <= 1e-12 * np.abs(A).max()
+    # the viscous dP/dFdot block is symmetric as well
+    mk = mats(orc, True)[name]
+    B = orc.tangent(mk, Hd, rng.normal(size=(3, 3)), 0.0, 1.0)
+    assert np.abs(B - B.transpose(2, 3, 0, 1)).max() <= 1e-12 * np.abs(B).max()
+
+
+def test_small_strain_limit_svk(orc):
+    E, nu = SVK_P
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = E / (2 * (1 + nu))
+    m = orc.material(orc.SVK, SVK_P)
+    rng = np.random.default_rng(13)
+    eps_scale = 1e-7
+    Hd = rand_hd(rng, eps_scale)
+    eps = 0.5 * (Hd + Hd.T)
+    hooke = lam * np.trace(eps) * np.eye(3) + 2 * mu * eps
+    P = orc.pk1(m, Hd)
+    assert np.abs(P - hooke).max() <= 1e-5 * np.abs(hooke).max()
+
+
+def test_small_strain_limit_mooney_rivlin(orc):
+    mu10, mu01, kap = MR_P
+    G = 2 * (mu10 + mu01)
+    m = orc.material(orc.MR, MR_P)
+    rng = np.random.default_rng(14)
+    Hd = rand_hd(rng, 1e-7)
+    eps = 0.5 * (Hd + Hd.T)
+    tr = np.trace(eps)
+    lin = kap * tr * np.eye(3) + 2 * G * (eps - tr / 3 * np.eye(3))
+    P = orc.pk1(m, Hd)
+    assert np.abs(P - lin).max() <= 1e-5 * np.abs(lin).max()
+
+
+def test_closed_form_energies(orc):
+    mu10, mu01, kap = MR_P
+    m = orc.material(orc.MR, MR_P)
+    # pure dilatation F = s I: isochoric invariants are 3
+    for s in (0.9, 1.0, 1.05, 1.3):
+        W = orc.energy_density(m, (s - 1) * np.eye(3))
+        assert abs(W - 0.5 * kap * (s ** 3 - 1) ** 2) <= 1e-9 * max(1.0, abs(W))
+    # isochoric uniaxial stretch: textbook incompressible Mooney-Rivlin energy
+    for lam in (0.7, 1.2, 1.6):
+        F = np.diag([lam, lam ** -0.5, lam ** -0.5])
+        W = orc.energy_density(m, F - np.eye(3))
+        ref = mu10 * (lam ** 2 + 2 / lam - 3) + mu01 * (2 * lam + 1 / lam ** 2 - 3)
+        assert abs(W - ref) <= 1e-8 * abs(ref)
+    # SVK uniaxial F = diag(s, 1, 1): E11 = (s^2 - 1)/2, W = (lam/2 + mu) E11^2
+    E, nu = SVK_P
+    lamL = E * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = E / (2 * (1 + nu))
+    msvk = orc.material(orc.SVK, SVK_P)
+    for s in (0.8, 1.1, 1.5):
+        W = orc.energy_density(msvk, np.diag([s - 1, 0, 0]))
+        E11 = 0.5 * (s * s - 1)
+        assert abs(W - (0.5 * lamL + mu) * E11 ** 2) <= 1e-9 * abs(W)
+
+
+def rot(rng):
+    Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] *= -1
+    return Q
+
+
+@pytest.mark.parametrize("name", ["svk", "mr"])
+def test_objectivity_and_spin(orc, name):
+    m = mats(orc, True)[name]
+    rng = np.random.default_rng(15)
+    for _ in range(3):
+        Hd = rand_hd(rng, 0.15)
+        F = np.eye(3) + Hd
+        Fd = rng.normal(size=(3, 3))
+        Q = rot(rng)
+        P = orc.pk1(m, Hd, Fd)
+        PQ = orc.pk1(m, Q @ F - np.eye(3), Q @ Fd)
+        assert np.abs(PQ - Q @ P).max() <= 1e-9 * np.abs(P).max()
+        # a pure spin rate Fdot = W F (W skew) produces no viscous stress
+        Wsk = rng.normal(size=(3, 3))
+        Wsk = Wsk - Wsk.T
+        Pe = orc.pk1(m, Hd, np.zeros((3, 3)))
+        Ps = orc.pk1(m, Hd, Wsk @ F)
+        assert np.abs(Ps - Pe).max() <= 1e-9 * np.abs(Pe).max()
+
+
+def test_viscous_newtonian_limit(orc):
+    # at F = I the Kelvin-Voigt stress is the Newtonian viscous stress
+    eta, lv = 3.0e4, 1.7e4
+    m = orc.material(orc.SVK, (0.0, 0.0), eta, lv)  # E = 0: viscous part only
+    rng = np.random.default_rng(16)
+    Fd = rng.normal(size=(3, 3))
+    P = orc.pk1(m, np.zeros((3, 3)), Fd)
+    ref = eta * (Fd + Fd.T) + lv * np.trace(Fd) * np.eye(3)
+    assert np.abs(P - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_jm1_accurate_near_identity(orc):
+    # the volumetric term uses J - 1 from the invariants of Hd, so tiny strains
+    # keep full relative accuracy: P_vol = kappa J (J-1) F^-T
+    m = orc.material(orc.MR, (0.0, 0.0, 1.0))
+    Hd = np.diag([1e-12, 2e-12, -0.5e-12])
+    P = orc.pk1(m, Hd)
+    jm1 = 2.5e-12  # to first order
+    assert abs(P[0, 0] - jm1) <= 1e-9 * jm1

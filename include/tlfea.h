@@ -1,0 +1,237 @@
+/*
+ * tlfea.h -- C ABI of the MI355X (gfx950) internal-force / tangent-stiffness
+ * library for total-Lagrangian finite elements (arXiv 2604.10357, Part II).
+ *
+ * The library evaluates, for T10 tetrahedra and ANCF3443 shells with
+ * Saint Venant-Kirchhoff or compressible Mooney-Rivlin stress plus optional
+ * Kelvin-Voigt damping:
+ *   - the internal force f_int(q, qdot)  (Sec. 4.3, Eqs. F_assembly,
+ *     fint_local, fint_global, atomic_scatter);
+ *   - the tangent  alpha * df/dq + beta * df/dqdot  scattered into a CSR
+ *     matrix whose pattern is built once (Sec. 4.2; Sec. 4.4.2,
+ *     Eq. tangent_block).  With (alpha, beta) = (h, 1) this is the Jacobian of
+ *     f_int(q_n + h v, v) with respect to v, the tangent term of the Newton
+ *     matrix H = M/h + h K_t + ... (Sec. 2, Eq. residual; Sec. 4.4.2,
+ *     Eq. hessian);
+ *   - vector-Jacobian products of f_int for reverse-mode differentiation.
+ *
+ * Conventions
+ *   - Every call returns a status: TLFEA_OK (0) or a negative error code;
+ *     tlfea_status_string() names it.  On error no output is written unless
+ *     the description says otherwise.
+ *   - Generalised coordinates are flat float64 arrays, DOF index
+ *     3 * coef + d.  T10: coef = node.  ANCF3443: coef = 4 * node + k with
+ *     k = 0..3 for (r, r_x, r_y, r_z).
+ *   - Arrays named d_* are DEVICE pointers owned by the caller (e.g. the
+ *     data_ptr of a torch tensor on the same GPU).  Arrays named h_* are host
+ *     pointers.  The library copies what it keeps; the caller may free its
+ *     arrays after a call returns.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Compute
+ *     calls only enqueue work on it and return without synchronising; their
+ *     outputs are valid once the stream reaches that point.  A mesh handle
+ *     must not be used by two streams at the same time.
+ *   - Outputs are overwritten (the library clears them on the stream); only
+ *     tlfea_assemble_accumulate adds into what the caller passes.
+ *   - The mesh handle owns device copies of connectivity, reference geometry,
+ *     the CSR pattern and the slot map; tlfea_mesh_destroy frees them.
+ */
+#ifndef TLFEA_H
+#define TLFEA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define TLFEA_OK 0
+#define TLFEA_ERR_INVALID -1         /* bad argument: null pointer, size, index out of range */
+#define TLFEA_ERR_UNSUPPORTED -2     /* element / material / rule / mesh feature not supported */
+#define TLFEA_ERR_DEGENERATE -3      /* a reference element has det J0 <= 0 */
+#define TLFEA_ERR_HIP -4             /* a HIP runtime call failed */
+#define TLFEA_ERR_NOMEM -5           /* device allocation failed */
+#define TLFEA_ERR_NO_PATTERN -6      /* call needs tlfea_build_csr_pattern first */
+#define TLFEA_ERR_TOO_LARGE -7       /* nnz or an index does not fit int32 */
+
+/* element types */
+#define TLFEA_T10 1        /* 10-node quadratic tetrahedron, 5-point Keast rule (Sec. 4.3) */
+#define TLFEA_ANCF3443 2   /* 4-node ANCF shell, nodes carry r, r_x, r_y, r_z (Sec. 4.3) */
+
+/* materials (Sec. 4.3, Stage 1) */
+#define TLFEA_SVK 1           /* params = {E, nu, unused} */
+#define TLFEA_MOONEY_RIVLIN 2 /* params = {mu10, mu01, kappa} */
+
+/* arithmetic of the element kernels */
+#define TLFEA_FP64 0   /* everything in float64 */
+#define TLFEA_MIXED 1  /* stress, material tangent and K_e in float32; displacement gradient,
+                          J - 1, J^(-2/3), J^(-4/3) and the volumetric coefficients in float64;
+                          global f and CSR accumulation in float64 */
+
+/* runtime flag bits (tlfea_get_runtime_flags) */
+#define TLFEA_FLAG_INVERTED 1u    /* some quadrature point had det F <= 0 */
+#define TLFEA_FLAG_NONFINITE 2u   /* some stress value was NaN or infinite */
+
+typedef struct tlfea_mesh_s* tlfea_mesh_t;
+typedef struct tlfea_batch_s* tlfea_batch_t;
+
+typedef struct {
+  int32_t elem_type;      /* TLFEA_T10 | TLFEA_ANCF3443 */
+  int64_t n_coef;         /* number of coefficient vectors (T10: nodes; ANCF: 4 * nodes) */
+  int64_t n_elem;
+  const int32_t* h_conn;  /* T10: n_elem x 10 node ids, corners then edges (0,1),(1,2),(0,2),
+                             (0,3),(1,3),(2,3); ANCF3443: n_elem x 4 node ids counter-clockwise
+                             from parent corner (-1,-1).  0-based. */
+  const double* h_X;      /* n_coef x 3 reference coefficients */
+  int32_t gl[3];          /* ANCF3443 Gauss-Legendre points per parent direction: {3,3,2} or
+                             {4,4,3}; ignored for T10 */
+  double thickness;       /* ANCF3443 shell thickness H; ignored for T10 */
+  int32_t material;       /* TLFEA_SVK | TLFEA_MOONEY_RIVLIN */
+  double params[3];       /* see the material constants above */
+  double kv_eta;          /* Kelvin-Voigt: S_v = 2 eta Edot + kv_lambda tr(Edot) I, P_v = F S_v */
+  double kv_lambda;       /* both 0 disables damping */
+  int32_t precision;      /* TLFEA_FP64 | TLFEA_MIXED */
+} tlfea_mesh_desc;
+
+/* Name of a status code (static string). */
+const char* tlfea_status_string(int status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int tlfea_version(void);
+
+/* Create a mesh on the current HIP device (Sec. 4.1: precompute once).
+ * Copies conn and X to the device and computes the reference Jacobians J0,
+ * det J0 and J0^-1 at every quadrature point (kept per element when an element
+ * is affine).  Validates ids and element sizes; returns TLFEA_ERR_DEGENERATE
+ * if any det J0 <= 0.  Synchronises the device.  *out is NULL on error. */
+int tlfea_mesh_create(const tlfea_mesh_desc* desc, tlfea_mesh_t* out);
+
+/* Free a mesh and everything it owns.  NULL is accepted. */
+int tlfea_mesh_destroy(tlfea_mesh_t mesh);
+
+/* Sizes: any pointer may be NULL.  nnz is -1 before the pattern is built. */
+int tlfea_mesh_info(tlfea_mesh_t mesh, int64_t* n_dof, int64_t* n_elem, int64_t* nnz,
+                    int32_t* n_en, int32_t* n_qp);
+
+/* Replace the material (same meaning as the descriptor fields). */
+int tlfea_mesh_set_material(tlfea_mesh_t mesh, int32_t material, const double params[3],
+                            double kv_eta, double kv_lambda);
+
+/* Switch between TLFEA_FP64 and TLFEA_MIXED element arithmetic. */
+int tlfea_mesh_set_precision(tlfea_mesh_t mesh, int32_t precision);
+
+/* Build the fixed CSR pattern of the DOF-level tangent and the slot map, once
+ * (Sec. 4.2; Sec. 4.4.2).  Two coefficients are adjacent iff their nodes share
+ * an element; every adjacent pair gives a full 3x3 block; rows are sorted.
+ * Runs on the device (incidence lists, per-node sort-unique, prefix sums) and
+ * synchronises.  Writes nnz (both triangles, structural zeros included).
+ * Returns TLFEA_ERR_TOO_LARGE if nnz exceeds INT32_MAX and
+ * TLFEA_ERR_UNSUPPORTED if a node is adjacent to more than 256 nodes (itself
+ * included) or gathers more than 4096 candidate neighbours. */
+int tlfea_build_csr_pattern(tlfea_mesh_t mesh, int64_t* nnz_out);
+
+/* Copy the CSR pattern out: row_offsets[n_dof + 1], col_indices[nnz] (int32).
+ * on_device != 0: destination pointers are device pointers (copy on `stream`
+ * without synchronising); 0: host pointers (synchronous). */
+int tlfea_get_csr_pattern(tlfea_mesh_t mesh, int32_t* row_offsets, int32_t* col_indices,
+                          int32_t on_device, void* stream);
+
+/* Export the canonical DOF-level slot map for elements [elem_begin,
+ * elem_begin + elem_count): slots[e][3a+i][3b+k] is the CSR position that
+ * receives entry (i, k) of block (a, b) of element e, (3 n_en)^2 int32 per
+ * element.  Destination semantics as in tlfea_get_csr_pattern. */
+int tlfea_get_slot_map(tlfea_mesh_t mesh, int64_t elem_begin, int64_t elem_count, int32_t* slots,
+                       int32_t on_device, void* stream);
+
+/* f_int(q, qdot) -> d_f (n_dof float64).  d_qdot may be NULL (zero velocity).
+ * Needs the pattern (tlfea_build_csr_pattern): the per-node reduction uses
+ * its node-to-element incidence.  The first call of each kind allocates the
+ * mesh's per-point work buffer (n_elem x n_qp records of 96 values, float32 in
+ * mixed precision) and synchronises; later calls do not allocate. */
+int tlfea_internal_force(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double* d_f,
+                         void* stream);
+
+/* CSR values of h * df/dq + df/dqdot = d f_int(q_n + h v, v) / dv -> d_vals (nnz). */
+int tlfea_tangent(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double h,
+                  double* d_vals, void* stream);
+
+/* CSR values of alpha * df/dq + beta * df/dqdot -> d_vals (nnz). */
+int tlfea_tangent_ex(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double alpha,
+                     double beta, double* d_vals, void* stream);
+
+/* Fused f_int and tangent (alpha, beta) = (h, 1) in one pass over the elements. */
+int tlfea_assemble(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double h,
+                   double* d_f, double* d_vals, void* stream);
+
+/* Fused f_int and tangent with explicit (alpha, beta). */
+int tlfea_assemble_ex(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double alpha,
+                      double beta, double* d_f, double* d_vals, void* stream);
+
+/* Same as tlfea_assemble_ex but ADDS into d_f and d_vals instead of
+ * overwriting them (either may be NULL to skip it).  Lets a caller add
+ * alpha * df/dq + beta * df/dqdot onto a matrix that already holds other terms
+ * of the Newton matrix, e.g. M/h in H = M/h + h K_t + ... (Sec. 4.4.2,
+ * Eq. hessian), without a separate clearing pass. */
+int tlfea_assemble_accumulate(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double alpha,
+                              double beta, double* d_f, double* d_vals, void* stream);
+
+/* The two passes of every assembly call, exposed so that a caller can put
+ * other work between them (e.g. pass 1 of the next mesh) or time them:
+ *   tlfea_assemble_points: per element and quadrature point, the constitutive
+ *     update (Sec. 4.3, Stage 1) and the point's stress and
+ *     alpha dP/dF + beta dP/dFdot in parent coordinates with the quadrature
+ *     volume folded in, stored in the mesh's work buffer (want_tangent = 0:
+ *     stress only).  Allocates the buffer on first use (synchronising).
+ *   tlfea_assemble_nodes: per node, the sums of Eqs. fint_local / fint_global
+ *     and Eq. tangent_block over the incident elements, written to d_f and / or
+ *     d_vals (either may be NULL; d_vals needs want_tangent = 1); accumulate
+ *     != 0 adds instead of overwriting.  Reads what the last
+ *     tlfea_assemble_points of the same mesh left; returns TLFEA_ERR_INVALID
+ *     if that does not exist, lacks the tangent or used another precision.
+ * tlfea_assemble_ex(...) is exactly tlfea_assemble_points(..., 1, s) followed
+ * by tlfea_assemble_nodes(..., 0, s). */
+int tlfea_assemble_points(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double alpha,
+                          double beta, int32_t want_tangent, void* stream);
+int tlfea_assemble_nodes(tlfea_mesh_t mesh, double* d_f, double* d_vals, int32_t accumulate,
+                         void* stream);
+
+/* Vector-Jacobian products of f_int for a cotangent w (n_dof):
+ *   d_gq     = (df/dq)^T w        (n_dof; may be NULL)
+ *   d_gqdot  = (df/dqdot)^T w     (n_dof; may be NULL)
+ *   d_gparam = d(w . f)/d(p0, p1, p2, kv_eta, kv_lambda)  (5 float64; may be NULL);
+ *              p = (E, nu, -) for SVK, (mu10, mu01, kappa) for Mooney-Rivlin. */
+int tlfea_internal_force_vjp(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot,
+                             const double* d_w, double* d_gq, double* d_gqdot, double* d_gparam,
+                             void* stream);
+
+/* Read (and synchronise on the mesh's last stream) the runtime flag bits,
+ * then clear them. */
+int tlfea_get_runtime_flags(tlfea_mesh_t mesh, uint32_t* flags);
+
+/* ---------------------------------------------------------------------------
+ * Batched assembly of many independent bodies in one launch.
+ * Each body keeps its own CSR (int32 within a body).  Body b owns
+ * q/qdot/f[dof_off[b] .. dof_off[b+1]) and vals[nnz_off[b] .. nnz_off[b+1]).
+ * All meshes must be of the same element type and have built patterns; they
+ * must stay alive while the batch exists.  Materials and precision are read
+ * from the meshes at tlfea_batch_create (mixed SVK / Mooney-Rivlin allowed).
+ * ------------------------------------------------------------------------- */
+int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, tlfea_batch_t* out);
+int tlfea_batch_destroy(tlfea_batch_t batch);
+
+/* Offsets (n_bodies + 1 each, host int64). */
+int tlfea_batch_offsets(tlfea_batch_t batch, int64_t* dof_off, int64_t* nnz_off);
+
+/* One launch over all bodies: f and tangent (h_b, 1) per body, h_b from the
+ * device array d_h (n_bodies float64). */
+int tlfea_batch_assemble(tlfea_batch_t batch, const double* d_q, const double* d_qdot,
+                         const double* d_h, double* d_f, double* d_vals, void* stream);
+
+/* Same as a loop of tlfea_assemble calls, one launch per body (reference path). */
+int tlfea_batch_assemble_loop(tlfea_batch_t batch, const double* d_q, const double* d_qdot,
+                              const double* d_h, double* d_f, double* d_vals, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TLFEA_H */

@@ -1,0 +1,215 @@
+"""Torch-facing wrappers over the C ABI.  PyTorch only provides device memory
+and the current stream; every step of the computation runs in the HIP kernels
+of ``libtlfea.so``."""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _native as N
+from .workloads import Material, Mesh
+
+_PREC = {"fp64": N.TLFEA_FP64, "mixed": N.TLFEA_MIXED}
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=torch.float64, n: Optional[int] = None) -> Optional[ctypes.c_void_p]:
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} CUDA tensor, got {t.dtype} on {t.device}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class TLMesh:
+    """One mesh handle: reference geometry, material, CSR pattern and slot map on the GPU."""
+
+    def __init__(self, mesh: Mesh, material: Material, precision: str = "fp64"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("TLMesh needs a HIP device")
+        L = N.lib()
+        conn = np.ascontiguousarray(mesh.conn, dtype=np.int32)
+        X = np.ascontiguousarray(mesh.X, dtype=np.float64)
+        d = N.MeshDesc()
+        d.elem_type = mesh.elem_type
+        d.n_coef = mesh.n_coef
+        d.n_elem = mesh.n_elem
+        d.h_conn = conn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.h_X = X.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.gl = (ctypes.c_int32 * 3)(*mesh.gl)
+        d.thickness = mesh.thickness
+        d.material = material.kind
+        p = list(material.params) + [0.0] * (3 - len(material.params))
+        d.params = (ctypes.c_double * 3)(*p[:3])
+        d.kv_eta = material.kv_eta
+        d.kv_lambda = material.kv_lambda
+        d.precision = _PREC[precision]
+        h = ctypes.c_void_p()
+        N.check(L.tlfea_mesh_create(ctypes.byref(d), ctypes.byref(h)), "tlfea_mesh_create")
+        self._h = h
+        self.mesh = mesh
+        self.material = material
+        self.precision = precision
+        self.n_dof = mesh.n_dof
+        self.n_elem = mesh.n_elem
+        self.n_en = 10 if mesh.elem_type == N.TLFEA_T10 else 16
+        self.nnz = -1
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            N.lib().tlfea_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- configuration
+    def set_material(self, material: Material):
+        p = list(material.params) + [0.0] * (3 - len(material.params))
+        arr = (ctypes.c_double * 3)(*p[:3])
+        N.check(N.lib().tlfea_mesh_set_material(self._h, material.kind, arr, material.kv_eta, material.kv_lambda),
+                "tlfea_mesh_set_material")
+        self.material = material
+
+    def set_precision(self, precision: str):
+        N.check(N.lib().tlfea_mesh_set_precision(self._h, _PREC[precision]), "tlfea_mesh_set_precision")
+        self.precision = precision
+
+    def info(self):
+        n_dof, n_el, nnz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        n_en, n_qp = ctypes.c_int32(), ctypes.c_int32()
+        N.check(N.lib().tlfea_mesh_info(self._h, ctypes.byref(n_dof), ctypes.byref(n_el), ctypes.byref(nnz),
+                                        ctypes.byref(n_en), ctypes.byref(n_qp)), "tlfea_mesh_info")
+        return dict(n_dof=n_dof.value, n_elem=n_el.value, nnz=nnz.value, n_en=n_en.value, n_qp=n_qp.value)
+
+    # -- pattern
+    def build_pattern(self) -> int:
+        nnz = ctypes.c_int64()
+        N.check(N.lib().tlfea_build_csr_pattern(self._h, ctypes.byref(nnz)), "tlfea_build_csr_pattern")
+        self.nnz = nnz.value
+        return self.nnz
+
+    def csr_pattern(self, on_device: bool = True):
+        dev = "cuda" if on_device else "cpu"
+        ro = torch.empty(self.n_dof + 1, dtype=torch.int32, device=dev)
+        cols = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)[: self.nnz]
+        N.check(N.lib().tlfea_get_csr_pattern(self._h, ctypes.c_void_p(ro.data_ptr()),
+                                              ctypes.c_void_p(cols.data_ptr()), int(on_device), _stream()),
+                "tlfea_get_csr_pattern")
+        return ro, cols
+
+    def slot_map(self, e0: int = 0, ne: Optional[int] = None, on_device: bool = True):
+        ne = self.n_elem - e0 if ne is None else ne
+        nd = 3 * self.n_en
+        dev = "cuda" if on_device else "cpu"
+        out = torch.empty((ne, nd, nd), dtype=torch.int32, device=dev)
+        N.check(N.lib().tlfea_get_slot_map(self._h, e0, ne, ctypes.c_void_p(out.data_ptr()), int(on_device),
+                                           _stream()), "tlfea_get_slot_map")
+        return out
+
+    # -- compute
+    def internal_force(self, q, qdot=None, out=None):
+        out = torch.empty(self.n_dof, dtype=torch.float64, device=q.device) if out is None else out
+        N.check(N.lib().tlfea_internal_force(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof),
+                                             _ptr(out, n=self.n_dof), _stream()), "tlfea_internal_force")
+        return out
+
+    def tangent(self, q, qdot=None, h: float = 1.0, out=None, alpha=None, beta=None):
+        out = torch.empty(self.nnz, dtype=torch.float64, device=q.device) if out is None else out
+        a = h if alpha is None else alpha
+        b = 1.0 if beta is None else beta
+        N.check(N.lib().tlfea_tangent_ex(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof), float(a),
+                                         float(b), _ptr(out, n=self.nnz), _stream()), "tlfea_tangent_ex")
+        return out
+
+    def assemble(self, q, qdot=None, alpha: float = 1.0, beta: float = 1.0, f=None, vals=None):
+        f = torch.empty(self.n_dof, dtype=torch.float64, device=q.device) if f is None else f
+        vals = torch.empty(self.nnz, dtype=torch.float64, device=q.device) if vals is None else vals
+        N.check(N.lib().tlfea_assemble_ex(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof), float(alpha),
+                                          float(beta), _ptr(f, n=self.n_dof), _ptr(vals, n=self.nnz), _stream()),
+                "tlfea_assemble_ex")
+        return f, vals
+
+    def assemble_accumulate(self, q, qdot=None, alpha: float = 1.0, beta: float = 1.0, f=None, vals=None):
+        N.check(N.lib().tlfea_assemble_accumulate(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof),
+                                                  float(alpha), float(beta), _ptr(f, n=self.n_dof),
+                                                  _ptr(vals, n=self.nnz), _stream()), "tlfea_assemble_accumulate")
+        return f, vals
+
+    def assemble_points(self, q, qdot=None, alpha: float = 1.0, beta: float = 1.0, want_tangent: bool = True):
+        N.check(N.lib().tlfea_assemble_points(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof),
+                                              float(alpha), float(beta), int(want_tangent), _stream()),
+                "tlfea_assemble_points")
+
+    def assemble_nodes(self, f=None, vals=None, accumulate: bool = False):
+        N.check(N.lib().tlfea_assemble_nodes(self._h, _ptr(f, n=self.n_dof), _ptr(vals, n=self.nnz),
+                                             int(accumulate), _stream()), "tlfea_assemble_nodes")
+        return f, vals
+
+    def vjp(self, q, qdot, w, want_q=True, want_qdot=True, want_params=True):
+        dev = q.device
+        gq = torch.empty(self.n_dof, dtype=torch.float64, device=dev) if want_q else None
+        gqd = torch.empty(self.n_dof, dtype=torch.float64, device=dev) if want_qdot else None
+        gp = torch.empty(5, dtype=torch.float64, device=dev) if want_params else None
+        N.check(N.lib().tlfea_internal_force_vjp(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof),
+                                                 _ptr(w, n=self.n_dof), _ptr(gq), _ptr(gqd), _ptr(gp), _stream()),
+                "tlfea_internal_force_vjp")
+        return gq, gqd, gp
+
+    def runtime_flags(self) -> int:
+        fl = ctypes.c_uint32()
+        N.check(N.lib().tlfea_get_runtime_flags(self._h, ctypes.byref(fl)), "tlfea_get_runtime_flags")
+        return fl.value
+
+
+class TLBatch:
+    """Many bodies assembled by one launch (per-body CSR kept)."""
+
+    def __init__(self, meshes: Sequence[TLMesh]):
+        self.meshes = list(meshes)
+        arr = (ctypes.c_void_p * len(self.meshes))(*[m.handle.value for m in self.meshes])
+        h = ctypes.c_void_p()
+        N.check(N.lib().tlfea_batch_create(arr, len(self.meshes), ctypes.byref(h)), "tlfea_batch_create")
+        self._h = h
+        n = len(self.meshes)
+        dof = (ctypes.c_int64 * (n + 1))()
+        nnz = (ctypes.c_int64 * (n + 1))()
+        N.check(N.lib().tlfea_batch_offsets(self._h, dof, nnz), "tlfea_batch_offsets")
+        self.dof_off = list(dof)
+        self.nnz_off = list(nnz)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.lib().tlfea_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def assemble(self, q, qdot, h, f=None, vals=None, loop: bool = False):
+        nd, nz = self.dof_off[-1], self.nnz_off[-1]
+        f = torch.empty(nd, dtype=torch.float64, device=q.device) if f is None else f
+        vals = torch.empty(nz, dtype=torch.float64, device=q.device) if vals is None else vals
+        fn = N.lib().tlfea_batch_assemble_loop if loop else N.lib().tlfea_batch_assemble
+        N.check(fn(self._h, _ptr(q, n=nd), _ptr(qdot, n=nd), _ptr(h, n=len(self.meshes)), _ptr(f, n=nd),
+                   _ptr(vals, n=nz), _stream()), "tlfea_batch_assemble")
+        return f, vals

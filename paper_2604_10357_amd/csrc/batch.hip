@@ -1,0 +1,200 @@
+// batch.hip -- many independent bodies assembled by one pair of launches.
+//
+// The paper runs one solver per body; for many small, uneven bodies a launch
+// per body leaves most of the GPU idle.  Here every body keeps its own mesh,
+// CSR pattern and slot map, and the batch concatenates their work: pass 1 runs
+// over the concatenated (element, point) indices of all bodies, pass 2 over
+// the concatenated node ranges, each workgroup writing into its body's slice
+// of the concatenated q / f / CSR value arrays.  On a non-default stream the
+// two launches are captured once into a HIP graph and replayed while the
+// argument pointers stay the same.
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "tlfea_internal.h"
+
+using tlfea::BatchArgs;
+using tlfea::BatchBody;
+using tlfea::BatchRange;
+
+struct tlfea_batch_s {
+  std::vector<tlfea_mesh_t> meshes;
+  int device = 0;
+  int elem_type = 0, gl0 = 0, precision = TLFEA_FP64;
+  std::vector<int64_t> dof_off, nnz_off;
+  BatchBody* d_bodies = nullptr;
+  BatchRange* d_ranges = nullptr;
+  int n_ranges = 0;
+  int64_t n_points = 0;
+  size_t lds = 0;
+  void* d_stage = nullptr;
+  uint32_t* d_flags = nullptr;
+  // graph cache, keyed by the argument pointers and the stream
+  hipGraphExec_t exec = nullptr;
+  const void* key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+static void batch_free(tlfea_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  (void)hipFree(b->d_bodies);
+  (void)hipFree(b->d_ranges);
+  (void)hipFree(b->d_stage);
+  (void)hipFree(b->d_flags);
+  delete b;
+}
+
+TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, tlfea_batch_t* out) {
+  if (!out) return TLFEA_ERR_INVALID;
+  *out = nullptr;
+  if (!meshes || n_bodies <= 0) return TLFEA_ERR_INVALID;
+  for (int i = 0; i < n_bodies; ++i) {
+    if (!meshes[i]) return TLFEA_ERR_INVALID;
+    if (!meshes[i]->m.has_pattern) return TLFEA_ERR_NO_PATTERN;
+  }
+  const tlfea::Mesh& m0 = meshes[0]->m;
+  auto* b = new (std::nothrow) tlfea_batch_s;
+  if (!b) return TLFEA_ERR_NOMEM;
+  b->device = m0.device;
+  b->elem_type = m0.elem_type;
+  b->gl0 = m0.gl[0];
+  b->precision = m0.precision;
+  std::vector<BatchBody> bodies(n_bodies);
+  std::vector<BatchRange> ranges;
+  b->dof_off.assign(n_bodies + 1, 0);
+  b->nnz_off.assign(n_bodies + 1, 0);
+  int64_t max_vals = 0;
+  for (int i = 0; i < n_bodies; ++i) {
+    const tlfea::Mesh& m = meshes[i]->m;
+    if (m.elem_type != b->elem_type || m.gl[0] != b->gl0 || m.precision != b->precision || m.device != b->device) {
+      delete b;
+      return TLFEA_ERR_INVALID;
+    }
+    BatchBody& B = bodies[i];
+    B.conn = m.d_conn;
+    B.X = m.d_X;
+    B.geo = m.d_geo;
+    B.escale = m.d_escale;
+    B.row_off = m.d_row_off;
+    B.rank = m.d_rank;
+    B.inc_off = m.d_inc_off;
+    B.inc = m.d_inc;
+    B.n_elem = m.n_elem;
+    B.dof_off = b->dof_off[i];
+    B.nnz_off = b->nnz_off[i];
+    B.point_off = b->n_points;
+    B.affine = m.affine ? 1 : 0;
+    B.half_h = 0.5 * m.thickness;
+    B.mp = m.mp;
+    b->dof_off[i + 1] = b->dof_off[i] + m.n_dof;
+    b->nnz_off[i + 1] = b->nnz_off[i] + m.nnz;
+    b->n_points += m.n_elem * m.n_qp;
+    for (int r = 0; r < m.n_ranges; ++r) ranges.push_back(BatchRange{i, m.h_ranges[r], m.h_ranges[r + 1]});
+    max_vals = std::max(max_vals, m.max_range_values);
+    b->meshes.push_back(meshes[i]);
+  }
+  if (ranges.size() > (size_t)INT32_MAX) { delete b; return TLFEA_ERR_TOO_LARGE; }
+  b->n_ranges = (int)ranges.size();
+  b->lds = sizeof(double) * (size_t)max_vals;
+  const size_t stage = (size_t)b->n_points * tlfea::stage_record_bytes(b->precision);
+  if (hipSetDevice(b->device) != hipSuccess) { delete b; return TLFEA_ERR_HIP; }
+  if (hipMalloc(&b->d_bodies, sizeof(BatchBody) * bodies.size()) != hipSuccess ||
+      hipMalloc(&b->d_ranges, sizeof(BatchRange) * (ranges.empty() ? 1 : ranges.size())) != hipSuccess ||
+      hipMalloc(&b->d_stage, stage > 0 ? stage : 1) != hipSuccess ||
+      hipMalloc(&b->d_flags, sizeof(uint32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    batch_free(b);
+    return TLFEA_ERR_NOMEM;
+  }
+  if (hipMemcpy(b->d_bodies, bodies.data(), sizeof(BatchBody) * bodies.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      (!ranges.empty() &&
+       hipMemcpy(b->d_ranges, ranges.data(), sizeof(BatchRange) * ranges.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemset(b->d_flags, 0, sizeof(uint32_t)) != hipSuccess) {
+    batch_free(b);
+    return TLFEA_ERR_HIP;
+  }
+  *out = b;
+  return TLFEA_OK;
+}
+
+TLFEA_API int tlfea_batch_destroy(tlfea_batch_t batch) {
+  if (!batch) return TLFEA_OK;
+  (void)hipSetDevice(batch->device);
+  (void)hipDeviceSynchronize();
+  batch_free(batch);
+  return TLFEA_OK;
+}
+
+TLFEA_API int tlfea_batch_offsets(tlfea_batch_t batch, int64_t* dof_off, int64_t* nnz_off) {
+  if (!batch) return TLFEA_ERR_INVALID;
+  if (dof_off) std::copy(batch->dof_off.begin(), batch->dof_off.end(), dof_off);
+  if (nnz_off) std::copy(batch->nnz_off.begin(), batch->nnz_off.end(), nnz_off);
+  return TLFEA_OK;
+}
+
+static int batch_enqueue(tlfea_batch_t b, const BatchArgs& a, hipStream_t s) {
+  return tlfea::launch_batch(b->elem_type, b->gl0, b->precision, a, b->n_ranges, b->lds, s);
+}
+
+TLFEA_API int tlfea_batch_assemble(tlfea_batch_t b, const double* d_q, const double* d_qdot, const double* d_h,
+                                   double* d_f, double* d_vals, void* stream) {
+  if (!b || !d_q || !d_h || !d_f || !d_vals) return TLFEA_ERR_INVALID;
+  if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
+  BatchArgs a{};
+  a.bodies = b->d_bodies;
+  a.ranges = b->d_ranges;
+  a.n_bodies = (int)b->meshes.size();
+  a.n_points = b->n_points;
+  a.stage = b->d_stage;
+  a.q = d_q;
+  a.qdot = d_qdot;
+  a.h = d_h;
+  a.f = d_f;
+  a.vals = d_vals;
+  a.flags = b->d_flags;
+  auto s = (hipStream_t)stream;
+  if (!s) return batch_enqueue(b, a, s);  // the legacy stream cannot be captured
+  const void* key[6] = {d_q, d_qdot, d_h, d_f, d_vals, stream};
+  if (!b->exec || !std::equal(key, key + 6, b->key)) {
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    TLFEA_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = batch_enqueue(b, a, s);
+    hipGraph_t g = nullptr;
+    hipError_t e1 = hipStreamEndCapture(s, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    TLFEA_HIP_CHECK(e1);
+    hipError_t e2 = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+      b->exec = nullptr;
+      (void)hipGetLastError();
+      return TLFEA_ERR_HIP;
+    }
+    std::copy(key, key + 6, b->key);
+  }
+  TLFEA_HIP_CHECK(hipGraphLaunch(b->exec, s));
+  return TLFEA_OK;
+}
+
+TLFEA_API int tlfea_batch_assemble_loop(tlfea_batch_t b, const double* d_q, const double* d_qdot,
+                                        const double* d_h, double* d_f, double* d_vals, void* stream) {
+  if (!b || !d_q || !d_h || !d_f || !d_vals) return TLFEA_ERR_INVALID;
+  if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
+  const size_t n = b->meshes.size();
+  std::vector<double> h(n);
+  auto s = (hipStream_t)stream;
+  TLFEA_HIP_CHECK(hipMemcpyAsync(h.data(), d_h, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  TLFEA_HIP_CHECK(hipStreamSynchronize(s));
+  for (size_t i = 0; i < n; ++i) {
+    int rc = tlfea_assemble_ex(b->meshes[i], d_q + b->dof_off[i], d_qdot ? d_qdot + b->dof_off[i] : nullptr, h[i],
+                               1.0, d_f + b->dof_off[i], d_vals + b->nnz_off[i], stream);
+    if (rc) return rc;
+  }
+  return TLFEA_OK;
+}

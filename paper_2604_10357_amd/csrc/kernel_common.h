@@ -1,0 +1,118 @@
+// kernel_common.h -- device helpers shared by the element kernels: tile
+// remapping, coefficient lookup, reference geometry and field gradients.
+#pragma once
+
+#include "rules.h"
+#include "tlfea_internal.h"
+
+namespace tlfea {
+namespace {
+
+// Workgroup b is dispatched to XCD b % 8; hand each XCD a contiguous tile range
+// so the CSR rows a tile touches are shared with its neighbours in one L2.
+__device__ __forceinline__ int remap_tile(int bid, int nblocks) {
+  const int xcd = bid & 7, idx = bid >> 3;
+  const int per = nblocks >> 3, extra = nblocks & 7;
+  return xcd * per + (xcd < extra ? xcd : extra) + idx;
+}
+
+template <class Rule>
+__device__ __forceinline__ int64_t coef_of(const int32_t* conn_e, int a) {
+  if constexpr (Rule::MC == 1) return conn_e[a];
+  else return 4 * (int64_t)conn_e[a >> 2] + (a & 3);
+}
+
+// element scale of each coefficient kind (ANCF: 1, lx/2, ly/2, H/2; T10: 1)
+template <class Rule>
+__device__ __forceinline__ void element_scales(const AsmArgs& a, int64_t ge, double* sc) {
+  if constexpr (Rule::MC == 1) {
+    sc[0] = sc[1] = sc[2] = sc[3] = 1.0;
+  } else {
+    sc[0] = 1.0;
+    sc[1] = a.escale[2 * ge];
+    sc[2] = a.escale[2 * ge + 1];
+    sc[3] = a.half_h;
+  }
+}
+
+template <class Rule>
+__device__ __forceinline__ void load_geometry(const AsmArgs& a, int64_t ge, int q, double* Jinv, double& det) {
+  const double* rec = a.geo + 10 * (a.affine ? ge : ge * Rule::NQ + q);
+#pragma unroll
+  for (int t = 0; t < 9; ++t) Jinv[t] = rec[t];
+  det = rec[9];
+}
+
+// Gradient  sum_a (u_a - X_a) (x) g_a  (X may be null) of a nodal field u at point q.
+// Formed as (sum_a u_a (x) dN_a) J0^-1: parent gradient first, then one 3x3 product.
+template <class Rule>
+__device__ __forceinline__ void field_gradient(const AsmArgs& a, int64_t ge, int q, const double* sc,
+                                               const double* u, const double* X, const double* Jinv,
+                                               double* out) {
+  const int32_t* conn_e = a.conn + ge * Rule::NPN;
+  double D[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) D[t] = 0.0;
+#pragma unroll
+  for (int al = 0; al < Rule::NEN; ++al) {
+    const int64_t c = coef_of<Rule>(conn_e, al);
+    const double s = sc[al % 4];
+    const double w0 = Rule::dN_rt(q, al, 0) * s, w1 = Rule::dN_rt(q, al, 1) * s,
+                 w2 = Rule::dN_rt(q, al, 2) * s;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double d = X ? u[3 * c + i] - X[3 * c + i] : u[3 * c + i];
+      D[3 * i] += d * w0;
+      D[3 * i + 1] += d * w1;
+      D[3 * i + 2] += d * w2;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int J = 0; J < 3; ++J)
+      out[3 * i + J] = D[3 * i] * Jinv[J] + D[3 * i + 1] * Jinv[3 + J] + D[3 * i + 2] * Jinv[6 + J];
+}
+
+// Hd = F - I and Fdot at point q of element ge (float64).
+template <class Rule>
+__device__ __forceinline__ void load_kinematics(const AsmArgs& a, int64_t ge, int q, double* Hd, double* Fd,
+                                                double* Jinv, double& det) {
+  load_geometry<Rule>(a, ge, q, Jinv, det);
+  double sc[4];
+  element_scales<Rule>(a, ge, sc);
+  field_gradient<Rule>(a, ge, q, sc, a.q, a.X, Jinv, Hd);
+  if (a.qdot) {
+    field_gradient<Rule>(a, ge, q, sc, a.qdot, nullptr, Jinv, Fd);
+  } else {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) Fd[t] = 0.0;
+  }
+}
+
+// the assembly arguments of body `bi` of a batch
+__device__ __forceinline__ AsmArgs body_args(const BatchArgs& b, const BatchBody& B, int bi) {
+  AsmArgs a;
+  a.conn = B.conn;
+  a.X = B.X;
+  a.geo = B.geo;
+  a.escale = B.escale;
+  a.half_h = B.half_h;
+  a.affine = B.affine;
+  a.n_elem = B.n_elem;
+  a.n_tiles = 0;
+  a.q = b.q + B.dof_off;
+  a.qdot = b.qdot ? b.qdot + B.dof_off : nullptr;
+  a.f = nullptr;
+  a.vals = nullptr;
+  a.row_off = B.row_off;
+  a.rank = B.rank;
+  a.mp = B.mp;
+  a.alpha = b.h[bi];
+  a.beta = 1.0;
+  a.flags = b.flags;
+  return a;
+}
+
+}  // namespace
+}  // namespace tlfea

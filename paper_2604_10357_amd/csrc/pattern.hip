@@ -1,0 +1,381 @@
+// pattern.hip -- fixed CSR pattern and slot map, built once on the GPU.
+//
+// Sec. 4.2 of the paper: the coefficient-level adjacency comes from element
+// connectivity, each adjacent pair of coefficients becomes a 3x3 DOF block
+// (Sec. 4.4.2), and the structure never changes afterwards, so Newton
+// iterations only rewrite values.  The paper sorts 64-bit pair keys on the
+// device; this builder instead goes through node -> element incidence lists:
+//   1. count and fill the incidence of every pattern node (atomics + scan);
+//   2. one wavefront per node gathers the nodes of its incident elements into
+//      LDS and ranks the distinct ones (sorted order, deterministic);
+//   3. prefix sums give the adjacency offsets and the DOF row offsets;
+//   4. columns are written per node; the slot map is stored as one byte per
+//      (element, node a, node b): the rank of b in the sorted adjacency of a.
+// A pattern node is a T10 node or an ANCF physical node (4 coefficients).
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <vector>
+
+#include "tlfea_internal.h"
+
+namespace tlfea {
+namespace {
+
+constexpr int kMaxCand = 4096;  // candidate neighbours per node held in LDS
+
+__global__ void k_count_inc(const int32_t* conn, int64_t n, int32_t* cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(cnt + conn[i], 1);
+}
+
+__global__ void k_fill_inc(const int32_t* conn, int64_t n, int npn, const int32_t* off, int32_t* cursor,
+                           int32_t* inc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int32_t node = conn[i];
+    const int32_t pos = atomicAdd(cursor + node, 1);
+    inc[off[node] + pos] = (int32_t)(i / npn);
+  }
+}
+
+// One wavefront per pattern node.  fill == 0: write the number of distinct
+// neighbours to nadj[I]; fill == 1: write them, sorted, to adj[adj_off[I]..].
+__global__ __launch_bounds__(64) void k_adjacency(const int32_t* conn, int npn, const int32_t* inc_off,
+                                                  const int32_t* inc, int64_t n_nodes, int fill,
+                                                  int32_t* nadj, const int32_t* adj_off, int32_t* adj,
+                                                  uint32_t* err) {
+  __shared__ int32_t cand[kMaxCand];
+  __shared__ uint8_t first[kMaxCand];
+  __shared__ int32_t count;
+  const int64_t I = blockIdx.x;
+  if (I >= n_nodes) return;
+  const int lane = threadIdx.x;
+  const int32_t b0 = inc_off[I], nin = inc_off[I + 1] - b0;
+  const int nc = nin * npn;
+  if (nc > kMaxCand) {
+    if (lane == 0) {
+      atomicOr(err, 1u);
+      if (!fill) nadj[I] = 0;
+    }
+    return;
+  }
+  if (lane == 0) count = 0;
+  for (int j = lane; j < nc; j += 64) cand[j] = conn[(int64_t)inc[b0 + j / npn] * npn + j % npn];
+  __syncthreads();
+  int mine = 0;
+  for (int j = lane; j < nc; j += 64) {
+    const int32_t v = cand[j];
+    bool f = true;
+    for (int k = 0; k < j; ++k)
+      if (cand[k] == v) { f = false; break; }
+    first[j] = f ? 1 : 0;
+    mine += f ? 1 : 0;
+  }
+  __syncthreads();
+  if (!fill) {
+    if (mine) atomicAdd(&count, mine);
+    __syncthreads();
+    if (lane == 0) nadj[I] = count;
+    return;
+  }
+  for (int j = lane; j < nc; j += 64) {
+    if (!first[j]) continue;
+    const int32_t v = cand[j];
+    int r = 0;
+    for (int k = 0; k < nc; ++k) r += (first[k] && cand[k] < v) ? 1 : 0;
+    adj[adj_off[I] + r] = v;
+  }
+}
+
+// per node: element id and the node's local index packed as (e << 4) | a,
+// sorted by element (insertion sort of a short list)
+__global__ void k_pack_inc(const int32_t* conn, int npn, const int32_t* inc_off, int32_t* inc, int64_t n_nodes) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= n_nodes) return;
+  const int32_t b0 = inc_off[I], b1 = inc_off[I + 1];
+  for (int32_t s = b0; s < b1; ++s) {
+    const int32_t e = inc[s];
+    int a = 0;
+    while (a < npn - 1 && conn[(int64_t)e * npn + a] != I) ++a;
+    int32_t v = (e << 4) | a;
+    int32_t t = s;
+    while (t > b0 && inc[t - 1] > v) {
+      inc[t] = inc[t - 1];
+      --t;
+    }
+    inc[t] = v;
+  }
+}
+
+__global__ void k_node_nnz(const int32_t* nadj, int64_t n, int64_t blk, int64_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = blk * nadj[i];
+}
+
+// row offsets: row 3 (mc I + c) + i starts at node_off[I] + (3c + i) * 3 mc nadj[I]
+__global__ void k_rows(const int64_t* node_off, const int32_t* nadj, int64_t n_nodes, int mc, int32_t* row_off,
+                       int64_t n_dof) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I < n_nodes) {
+    const int64_t len = 3LL * mc * nadj[I];
+    for (int r = 0; r < 3 * mc; ++r) row_off[3LL * mc * I + r] = (int32_t)(node_off[I] + r * len);
+  }
+  if (I == 0) row_off[n_dof] = (int32_t)node_off[n_nodes];
+}
+
+// columns of all rows of node I, one wavefront per node
+__global__ __launch_bounds__(64) void k_cols(const int32_t* adj_off, const int32_t* adj, const int32_t* row_off,
+                                             int64_t n_nodes, int mc, int32_t* cols) {
+  const int64_t I = blockIdx.x;
+  if (I >= n_nodes) return;
+  const int32_t a0 = adj_off[I], na = adj_off[I + 1] - a0;
+  const int rl = 3 * mc * na;   // row length
+  const int total = 3 * mc * rl;
+  for (int t = threadIdx.x; t < total; t += 64) {
+    const int r = t / rl, col = t % rl;           // local row (c, i), column position
+    const int jr = col / (3 * mc), rest = col % (3 * mc);  // rank of neighbour, (c', k)
+    const int64_t J = adj[a0 + jr];
+    cols[(int64_t)row_off[3LL * mc * I + r] + col] = (int32_t)(3 * mc * J + rest);
+  }
+}
+
+// rank[e][p][p'] = position of node conn[e][p'] in the sorted adjacency of conn[e][p]
+__global__ void k_rank(const int32_t* conn, int64_t n_elem, int npn, const int32_t* adj_off,
+                       const int32_t* adj, uint8_t* rank, uint32_t* err) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = n_elem * npn * npn;
+  if (t >= total) return;
+  const int64_t e = t / (npn * npn);
+  const int p = (int)((t / npn) % npn), pb = (int)(t % npn);
+  const int32_t a = conn[e * npn + p], b = conn[e * npn + pb];
+  int lo = adj_off[a], hi = adj_off[a + 1] - 1;
+  int found = -1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int32_t v = adj[mid];
+    if (v == b) { found = mid; break; }
+    if (v < b) lo = mid + 1; else hi = mid - 1;
+  }
+  const int r = found - adj_off[a];
+  if (found < 0 || r > 255) {
+    atomicOr(err, 2u);
+    rank[t] = 0;
+  } else {
+    rank[t] = (uint8_t)r;
+  }
+}
+
+__global__ void k_slots(const int32_t* conn, int64_t e0, int64_t ne, int npn, int mc, int nen,
+                        const int32_t* row_off, const uint8_t* rank, int32_t* out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nd = 3 * nen;
+  const int64_t total = ne * nd * nd;
+  if (t >= total) return;
+  const int64_t el = t / (nd * nd);
+  const int r = (int)((t / nd) % nd), c = (int)(t % nd);
+  const int64_t e = e0 + el;
+  const int al = r / 3, i = r % 3, be = c / 3, k = c % 3;
+  const int pa = al / mc, ca = al % mc, pb = be / mc, cb = be % mc;
+  const int64_t coef_a = (int64_t)mc * conn[e * npn + pa] + ca;
+  const int64_t base = row_off[3 * coef_a + i];
+  out[t] = (int32_t)(base + 3 * (mc * (int64_t)rank[(e * npn + pa) * npn + pb] + cb) + k);
+}
+
+int grid_of(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
+template <typename T>
+int scan_exclusive(const T* in, T* out, int64_t n, hipStream_t s) {
+  size_t bytes = 0;
+  TLFEA_HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, s));
+  void* tmp = nullptr;
+  TLFEA_HIP_CHECK(hipMalloc(&tmp, bytes > 0 ? bytes : 1));
+  hipError_t err = hipcub::DeviceScan::ExclusiveSum(tmp, bytes, in, out, (int)n, s);
+  hipError_t err2 = hipStreamSynchronize(s);
+  (void)hipFree(tmp);
+  TLFEA_HIP_CHECK(err);
+  TLFEA_HIP_CHECK(err2);
+  return TLFEA_OK;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+}  // namespace
+
+int build_pattern(Mesh& m) {
+  hipStream_t s = nullptr;
+  const int npn = m.n_pn, mc = m.mc;
+  const int64_t nn = m.n_pnodes, ninc = m.n_elem * npn;
+  if (nn + 1 > INT32_MAX || ninc > INT32_MAX || m.n_elem >= (1LL << 27)) return TLFEA_ERR_TOO_LARGE;
+  DevBuf cnt, inc_off, cursor, inc, nadj, node_nnz, node_off, err;
+  TLFEA_HIP_CHECK(hipMalloc(&cnt.p, sizeof(int32_t) * (nn + 1)));
+  TLFEA_HIP_CHECK(hipMalloc(&inc_off.p, sizeof(int32_t) * (nn + 1)));
+  TLFEA_HIP_CHECK(hipMalloc(&cursor.p, sizeof(int32_t) * (nn + 1)));
+  TLFEA_HIP_CHECK(hipMalloc(&inc.p, sizeof(int32_t) * (ninc > 0 ? ninc : 1)));
+  // ownership of the incidence lists passes to the mesh on success
+  int32_t* d_inc_off = (int32_t*)inc_off.p;
+  int32_t* d_inc = (int32_t*)inc.p;
+  TLFEA_HIP_CHECK(hipMalloc(&nadj.p, sizeof(int32_t) * (nn + 1)));
+  TLFEA_HIP_CHECK(hipMalloc(&node_nnz.p, sizeof(int64_t) * (nn + 1)));
+  TLFEA_HIP_CHECK(hipMalloc(&node_off.p, sizeof(int64_t) * (nn + 1)));
+  TLFEA_HIP_CHECK(hipMalloc(&err.p, sizeof(uint32_t)));
+  TLFEA_HIP_CHECK(hipMemset(cnt.p, 0, sizeof(int32_t) * (nn + 1)));
+  TLFEA_HIP_CHECK(hipMemset(cursor.p, 0, sizeof(int32_t) * (nn + 1)));
+  TLFEA_HIP_CHECK(hipMemset(nadj.p, 0, sizeof(int32_t) * (nn + 1)));
+  TLFEA_HIP_CHECK(hipMemset(node_nnz.p, 0, sizeof(int64_t) * (nn + 1)));
+  TLFEA_HIP_CHECK(hipMemset(err.p, 0, sizeof(uint32_t)));
+  auto* d_cnt = (int32_t*)cnt.p;
+  auto* d_nadj = (int32_t*)nadj.p;
+  auto* d_err = (uint32_t*)err.p;
+
+  if (ninc > 0)
+    hipLaunchKernelGGL(k_count_inc, dim3(grid_of(ninc, 256)), dim3(256), 0, s, m.d_conn, ninc, d_cnt);
+  TLFEA_HIP_CHECK(hipGetLastError());
+  int rc = scan_exclusive<int32_t>(d_cnt, d_inc_off, nn + 1, s);
+  if (rc) return rc;
+  if (ninc > 0)
+    hipLaunchKernelGGL(k_fill_inc, dim3(grid_of(ninc, 256)), dim3(256), 0, s, m.d_conn, ninc, npn, d_inc_off,
+                       (int32_t*)cursor.p, d_inc);
+  TLFEA_HIP_CHECK(hipGetLastError());
+
+  if (nn > 0)
+    hipLaunchKernelGGL(k_adjacency, dim3((unsigned)nn), dim3(64), 0, s, m.d_conn, npn, d_inc_off, d_inc, nn, 0,
+                       d_nadj, nullptr, nullptr, d_err);
+  TLFEA_HIP_CHECK(hipGetLastError());
+  uint32_t herr = 0;
+  TLFEA_HIP_CHECK(hipMemcpy(&herr, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  if (herr) return TLFEA_ERR_UNSUPPORTED;
+
+  // adjacency offsets
+  int32_t* d_adj_off = nullptr;
+  TLFEA_HIP_CHECK(hipMalloc(&d_adj_off, sizeof(int32_t) * (nn + 1)));
+  rc = scan_exclusive<int32_t>(d_nadj, d_adj_off, nn + 1, s);
+  if (rc) { (void)hipFree(d_adj_off); return rc; }
+  int32_t n_adj_total = 0;
+  TLFEA_HIP_CHECK(hipMemcpy(&n_adj_total, d_adj_off + nn, sizeof(int32_t), hipMemcpyDeviceToHost));
+  int32_t* d_adj = nullptr;
+  TLFEA_HIP_CHECK(hipMalloc(&d_adj, sizeof(int32_t) * (n_adj_total > 0 ? n_adj_total : 1)));
+  if (nn > 0)
+    hipLaunchKernelGGL(k_adjacency, dim3((unsigned)nn), dim3(64), 0, s, m.d_conn, npn, d_inc_off, d_inc, nn, 1,
+                       d_nadj, d_adj_off, d_adj, d_err);
+  TLFEA_HIP_CHECK(hipGetLastError());
+
+  // DOF rows: every neighbour contributes a (3 mc) x (3 mc) block
+  const int64_t blk = 9LL * mc * mc;
+  if (nn > 0)
+    hipLaunchKernelGGL(k_node_nnz, dim3(grid_of(nn, 256)), dim3(256), 0, s, d_nadj, nn, blk,
+                       (int64_t*)node_nnz.p);
+  TLFEA_HIP_CHECK(hipGetLastError());
+  rc = scan_exclusive<int64_t>((int64_t*)node_nnz.p, (int64_t*)node_off.p, nn + 1, s);
+  if (rc) { (void)hipFree(d_adj_off); (void)hipFree(d_adj); return rc; }
+  int64_t nnz = 0;
+  TLFEA_HIP_CHECK(hipMemcpy(&nnz, (int64_t*)node_off.p + nn, sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (nnz > INT32_MAX) { (void)hipFree(d_adj_off); (void)hipFree(d_adj); return TLFEA_ERR_TOO_LARGE; }
+
+  int32_t *d_row_off = nullptr, *d_cols = nullptr;
+  uint8_t* d_rank = nullptr;
+  if (hipMalloc(&d_row_off, sizeof(int32_t) * (m.n_dof + 1)) != hipSuccess ||
+      hipMalloc(&d_cols, sizeof(int32_t) * (nnz > 0 ? nnz : 1)) != hipSuccess ||
+      hipMalloc(&d_rank, (size_t)(m.n_elem * npn * npn > 0 ? m.n_elem * npn * npn : 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(d_row_off); (void)hipFree(d_cols); (void)hipFree(d_rank);
+    (void)hipFree(d_adj_off); (void)hipFree(d_adj);
+    return TLFEA_ERR_NOMEM;
+  }
+  hipLaunchKernelGGL(k_rows, dim3(grid_of(nn > 0 ? nn : 1, 256)), dim3(256), 0, s, (int64_t*)node_off.p, d_nadj,
+                     nn, mc, d_row_off, m.n_dof);
+  if (nn > 0)
+    hipLaunchKernelGGL(k_cols, dim3((unsigned)nn), dim3(64), 0, s, d_adj_off, d_adj, d_row_off, nn, mc, d_cols);
+  const int64_t nrank = m.n_elem * npn * npn;
+  if (nrank > 0)
+    hipLaunchKernelGGL(k_rank, dim3(grid_of(nrank, 256)), dim3(256), 0, s, m.d_conn, m.n_elem, npn, d_adj_off,
+                       d_adj, d_rank, d_err);
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipDeviceSynchronize();
+  uint32_t herr2 = 0;
+  hipError_t e3 = hipMemcpy(&herr2, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || herr2) {
+    (void)hipFree(d_row_off); (void)hipFree(d_cols); (void)hipFree(d_rank);
+    (void)hipFree(d_adj_off); (void)hipFree(d_adj);
+    if (herr2) return TLFEA_ERR_UNSUPPORTED;
+    return TLFEA_ERR_HIP;
+  }
+  // packed, sorted incidence for pass 2
+  if (nn > 0)
+    hipLaunchKernelGGL(k_pack_inc, dim3(grid_of(nn, 128)), dim3(128), 0, s, m.d_conn, npn, d_inc_off, d_inc, nn);
+  std::vector<int32_t> h_inc_off(nn + 1), h_adj_off(nn + 1);
+  hipError_t e4 = hipGetLastError();
+  hipError_t e5 = hipMemcpy(h_inc_off.data(), d_inc_off, sizeof(int32_t) * (nn + 1), hipMemcpyDeviceToHost);
+  hipError_t e6 = hipMemcpy(h_adj_off.data(), d_adj_off, sizeof(int32_t) * (nn + 1), hipMemcpyDeviceToHost);
+  // greedy partition of the nodes into ranges of bounded tasks and LDS values
+  std::vector<int32_t> ranges{0};
+  int64_t max_vals = 0, max_rows = 0;
+  {
+    int64_t tasks = 0, vals = 0, rows = 0, nodes = 0;
+    for (int64_t I = 0; I < nn; ++I) {
+      const int64_t tI = 3LL * mc * (h_inc_off[I + 1] - h_inc_off[I]);
+      const int64_t vI = 9LL * mc * mc * (h_adj_off[I + 1] - h_adj_off[I]) + 3LL * mc;
+      if (nodes > 0 && (tasks + tI > kRangeTasks || vals + vI > kRangeValues || nodes >= kMaxRangeNodes)) {
+        ranges.push_back((int32_t)I);
+        max_vals = std::max(max_vals, vals);
+        max_rows = std::max(max_rows, rows);
+        tasks = vals = rows = nodes = 0;
+      }
+      tasks += tI;
+      vals += vI;
+      rows += 3LL * mc;
+      ++nodes;
+    }
+    if (nodes > 0) {
+      ranges.push_back((int32_t)nn);
+      max_vals = std::max(max_vals, vals);
+      max_rows = std::max(max_rows, rows);
+    }
+  }
+  int32_t* d_ranges = nullptr;
+  hipError_t e7 = hipMalloc(&d_ranges, sizeof(int32_t) * ranges.size());
+  hipError_t e8 = e7 == hipSuccess ? hipMemcpy(d_ranges, ranges.data(), sizeof(int32_t) * ranges.size(),
+                                               hipMemcpyHostToDevice)
+                                   : e7;
+  if (e4 != hipSuccess || e5 != hipSuccess || e6 != hipSuccess || e8 != hipSuccess ||
+      max_vals * (int64_t)sizeof(double) > 64 * 1024) {
+    (void)hipFree(d_row_off); (void)hipFree(d_cols); (void)hipFree(d_rank);
+    (void)hipFree(d_adj_off); (void)hipFree(d_adj); (void)hipFree(d_ranges);
+    return max_vals * (int64_t)sizeof(double) > 64 * 1024 ? TLFEA_ERR_UNSUPPORTED : TLFEA_ERR_HIP;
+  }
+  // replace a previous pattern, if any
+  (void)hipFree(m.d_row_off); (void)hipFree(m.d_cols); (void)hipFree(m.d_rank);
+  (void)hipFree(m.d_adj_off); (void)hipFree(m.d_adj); (void)hipFree(m.d_ranges);
+  (void)hipFree(m.d_inc_off); (void)hipFree(m.d_inc);
+  m.d_row_off = d_row_off;
+  m.d_cols = d_cols;
+  m.d_rank = d_rank;
+  m.d_adj_off = d_adj_off;
+  m.d_adj = d_adj;
+  inc_off.p = nullptr;
+  inc.p = nullptr;
+  m.d_inc_off = d_inc_off;
+  m.d_inc = d_inc;
+  m.d_ranges = d_ranges;
+  m.h_ranges = std::move(ranges);
+  m.n_ranges = (int)m.h_ranges.size() - 1;
+  m.max_range_values = max_vals;
+  m.max_range_rows = max_rows;
+  m.nnz = nnz;
+  m.has_pattern = true;
+  return TLFEA_OK;
+}
+
+int export_slot_map(const Mesh& m, int64_t e0, int64_t ne, int32_t* d_out, hipStream_t s) {
+  const int64_t total = ne * 9LL * m.n_en * m.n_en;
+  if (total <= 0) return TLFEA_OK;
+  hipLaunchKernelGGL(k_slots, dim3(grid_of(total, 256)), dim3(256), 0, s, m.d_conn, e0, ne, m.n_pn, m.mc, m.n_en,
+                     m.d_row_off, m.d_rank, d_out);
+  TLFEA_HIP_CHECK(hipGetLastError());
+  return TLFEA_OK;
+}
+
+}  // namespace tlfea

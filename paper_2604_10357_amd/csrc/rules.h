@@ -1,0 +1,56 @@
+// rules.h -- element rules (shape-function tables, quadrature) for the kernels.
+//
+// Each translation unit that includes this header gets its own __constant__
+// copy of the tables (internal linkage) for run-time indexing; compile-time
+// indexing goes through the constexpr tables of tables.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "tables.h"
+
+namespace tlfea {
+namespace {
+
+static __constant__ T10Table c_t10 = make_t10_table();
+static __constant__ AncfTable<3, 3, 2> c_a332 = make_ancf_table<3, 3, 2>();
+static __constant__ AncfTable<4, 4, 3> c_a443 = make_ancf_table<4, 4, 3>();
+
+template <int N>
+struct Int {
+  static constexpr int value = N;
+};
+
+template <int I, int N, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (I < N) {
+    f(Int<I>{});
+    sfor<I + 1, N>(f);
+  }
+}
+
+struct RuleT10 {
+  static constexpr int NEN = 10, NPN = 10, MC = 1, NQ = 5;
+  static constexpr double dN(int q, int a, int m) { return kT10.dN[q][a][m]; }
+  __device__ static double dN_rt(int q, int a, int m) { return c_t10.dN[q][a][m]; }
+  __device__ static double w_rt(int q) { return c_t10.w[q]; }
+};
+
+template <int NX, int NY, int NZ>
+struct RuleAncf {
+  static constexpr int NEN = 16, NPN = 4, MC = 4, NQ = NX * NY * NZ;
+  static constexpr const AncfTable<NX, NY, NZ>& tab() {
+    if constexpr (NX == 3) return kAncf332; else return kAncf443;
+  }
+  static constexpr double dN(int q, int a, int m) { return tab().dS[q][a][m]; }
+  __device__ static const AncfTable<NX, NY, NZ>& ctab() {
+    if constexpr (NX == 3) return c_a332; else return c_a443;
+  }
+  __device__ static double dN_rt(int q, int a, int m) { return ctab().dS[q][a][m]; }
+  __device__ static double w_rt(int q) { return ctab().w[q]; }
+};
+
+}  // namespace
+}  // namespace tlfea

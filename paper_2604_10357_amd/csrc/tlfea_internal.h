@@ -1,0 +1,177 @@
+// tlfea_internal.h -- private declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/tlfea.h"
+#include "material.h"
+
+#define TLFEA_API extern "C" __attribute__((visibility("default")))
+
+#define TLFEA_HIP_CHECK(expr)                     \
+  do {                                            \
+    hipError_t err__ = (expr);                    \
+    if (err__ != hipSuccess) {                    \
+      (void)hipGetLastError();                    \
+      return err__ == hipErrorOutOfMemory ? TLFEA_ERR_NOMEM : TLFEA_ERR_HIP; \
+    }                                             \
+  } while (0)
+
+namespace tlfea {
+
+// Per-mesh state.  All d_* members are device allocations owned by the mesh.
+struct Mesh {
+  int device = 0;
+  int elem_type = 0;
+  int n_en = 0;        // shape functions (coefficient vectors) per element
+  int n_pn = 0;        // pattern nodes per element (T10: 10 nodes; ANCF: 4 physical nodes)
+  int mc = 0;          // coefficient vectors per pattern node (T10: 1; ANCF: 4)
+  int n_qp = 0;
+  int gl[3] = {0, 0, 0};
+  int64_t n_elem = 0, n_coef = 0, n_pnodes = 0, n_dof = 0;
+  double thickness = 0.0;
+  int precision = TLFEA_FP64;
+  int material = 0;
+  double params[3] = {0, 0, 0};
+  double kv_eta = 0, kv_lambda = 0;
+  MatParams mp{};
+
+  int32_t* d_conn = nullptr;      // n_elem * n_pn
+  double* d_X = nullptr;          // n_coef * 3
+  double* d_geo = nullptr;        // records of {J0^-1 (9, row-major [m][J]), det J0}
+  bool affine = false;            // true: one record per element; false: per (element, qp)
+  double* d_escale = nullptr;     // ANCF: per element {lx/2, ly/2}
+  uint32_t* d_flags = nullptr;    // runtime flags
+  double* d_vjp_acc = nullptr;    // 5 partial sums of the parameter VJP
+
+  // pass-2 work partition: node ranges whose CSR rows form one contiguous segment
+  int32_t* d_inc_off = nullptr;   // n_pnodes + 1, node -> incident elements
+  int32_t* d_inc = nullptr;       // (element << 4) | local node index, sorted by element per node
+  int32_t* d_ranges = nullptr;    // n_ranges + 1 node boundaries
+  std::vector<int32_t> h_ranges;
+  int n_ranges = 0;
+  int64_t max_range_values = 0;   // largest LDS segment (CSR values + force rows), in doubles
+  int64_t max_range_rows = 0;     // largest number of force rows of a range
+  void* d_stage = nullptr;        // pass-1 records
+  size_t stage_cap = 0;
+  int staged = 0;                 // what the last pass 1 left: 0 none, 1 force records, 2 force + tangent
+  int staged_precision = -1;
+
+  bool has_pattern = false;
+  int64_t nnz = -1;
+  int32_t* d_row_off = nullptr;   // n_dof + 1
+  int32_t* d_cols = nullptr;      // nnz
+  int32_t* d_adj_off = nullptr;   // n_pnodes + 1, pattern-node adjacency
+  int32_t* d_adj = nullptr;
+  uint8_t* d_rank = nullptr;      // n_elem * n_pn * n_pn: rank of node b in adj(node a)
+  hipStream_t last_stream = nullptr;
+};
+
+// Everything one assembly launch needs (passed by value to the kernels).
+struct AsmArgs {
+  const int32_t* conn;
+  const double* X;
+  const double* geo;
+  const double* escale;
+  double half_h;       // ANCF thickness / 2
+  int affine;
+  int64_t n_elem;
+  int n_tiles;
+  const double* q;
+  const double* qdot;  // may be null
+  double* f;           // may be null
+  double* vals;        // may be null
+  const int32_t* row_off;
+  const uint8_t* rank;
+  MatParams mp;
+  double alpha, beta;
+  uint32_t* flags;
+};
+
+constexpr int kMaxRangeNodes = 64;      // nodes per pass-2 workgroup
+constexpr int kRangeTasks = 256;        // target tasks (lanes) per pass-2 workgroup
+constexpr int kRangeValues = 4096;      // target LDS doubles per pass-2 workgroup
+
+// Pass-2 arguments of one mesh.
+struct GatherArgs {
+  const int32_t* ranges;
+  const int32_t* inc_off;
+  const int32_t* inc;
+  const int32_t* row_off;
+  const uint8_t* rank;
+  const double* escale;
+  double half_h;
+  const void* stage;
+  double* f;
+  double* vals;
+};
+
+// Batched launch: one descriptor per body; pass 1 runs over the concatenated
+// (element, point) indices, pass 2 over the concatenated node ranges.
+struct BatchBody {
+  const int32_t* conn;
+  const double* X;
+  const double* geo;
+  const double* escale;
+  const int32_t* row_off;
+  const uint8_t* rank;
+  const int32_t* inc_off;
+  const int32_t* inc;
+  int64_t n_elem, dof_off, nnz_off, point_off;
+  int affine;
+  double half_h;
+  MatParams mp;
+};
+struct BatchRange {
+  int32_t body, I0, I1;
+};
+struct BatchArgs {
+  const BatchBody* bodies;
+  const BatchRange* ranges;
+  int n_bodies;
+  int64_t n_points;
+  void* stage;
+  const double* q;
+  const double* qdot;
+  const double* h;   // per body
+  double* f;
+  double* vals;
+  uint32_t* flags;
+};
+
+MatParams make_params(int material, const double* params, double eta, double lam_v);
+
+// bytes of pass-1 records for a mesh / per record
+size_t stage_bytes(const Mesh& m, bool want_k);
+size_t stage_record_bytes(int precision);
+int launch_batch(int elem_type, int gl0, int precision, const BatchArgs& b, int n_ranges, size_t lds,
+                 hipStream_t s);
+
+// kernel launchers (assemble.hip)
+int launch_zero(double* p, int64_t n, hipStream_t s);
+// pass 1: per-point records into m.d_stage; pass 2: per-node reduction into f / vals
+int launch_points(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s);
+int launch_nodes(const Mesh& m, double* f, double* vals, bool accumulate, hipStream_t s);
+
+// pattern builder (pattern.hip)
+int build_pattern(Mesh& m);
+int export_slot_map(const Mesh& m, int64_t e0, int64_t ne, int32_t* d_out, hipStream_t s);
+
+// geometry precompute (mesh.hip)
+int precompute_geometry(Mesh& m);
+
+// VJP (vjp.hip)
+int launch_vjp(const Mesh& m, const double* q, const double* qdot, const double* w, double* gq,
+               double* gqdot, double* gparam, hipStream_t s);
+
+AsmArgs make_args(const Mesh& m, const double* q, const double* qdot, double* f, double* vals,
+                  double alpha, double beta);
+
+}  // namespace tlfea
+
+struct tlfea_mesh_s {
+  tlfea::Mesh m;
+};

@@ -247,8 +247,10 @@ def batched_bodies(n_bodies: int = 512, seed: int = 1004, n_lo: int = 2, n_hi: i
         s = rng.uniform(0.8, 1.2, size=4)
         eta = MR_BASE["eta"] * s[3]
         if b % 2 == 0:
-            E, nu = svk_from_mr(MR_BASE["mu10"], MR_BASE["mu01"], MR_BASE["kappa"])
-            mats.append(Material(SVK, (E * s[0], nu * s[1], 0.0), eta, eta))
+            # SVK: scale the shear modulus 2(mu10+mu01) and the bulk modulus kappa
+            # (scaling nu itself could push it past 1/2), then convert to (E, nu)
+            E, nu = svk_from_mr(MR_BASE["mu10"] * s[0], MR_BASE["mu01"] * s[0], MR_BASE["kappa"] * s[2])
+            mats.append(Material(SVK, (E, nu, 0.0), eta, eta))
         else:
             mats.append(Material(MOONEY_RIVLIN, (MR_BASE["mu10"] * s[0], MR_BASE["mu01"] * s[1],
                                                  MR_BASE["kappa"] * s[2]), eta, eta))

@@ -17,7 +17,8 @@
 //     store the point's tangent and stress in parent coordinates with the
 //     quadrature volume folded in,
 //        Ahat_imkn = dV sum_JL J0inv_mJ A_iJkL J0inv_nL,  Phat_im = dV sum_J P_iJ J0inv_mJ,
-//     as one 96-value record (81 + 9 + padding).
+//     as one 96-value record: Ahat row i at [28 i, 28 i + 27), Phat row i at
+//     [84 + 4 i, 84 + 4 i + 3), so that every row starts on 16 bytes.
 //   pass 2 (k_gather, one workgroup per contiguous range of nodes): the CSR
 //     rows of consecutive nodes form one contiguous segment, mirrored in LDS.
 //     Each lane owns one (node, incident element, coefficient row) task and
@@ -34,8 +35,10 @@
 namespace tlfea {
 namespace {
 
-constexpr int kRecK = 96;  // record length with tangent: Ahat (81) + Phat (9) + pad
+constexpr int kRecK = 96;  // record length with tangent: Ahat rows padded to 28, Phat rows padded to 4
 constexpr int kRecF = 12;  // record length for the force only: Phat rows padded to 4
+constexpr int kRowA = 28;  // Ahat row stride within a record
+constexpr int kOffP = 84;  // Phat offset within a tangent record
 
 // ---------------------------------------------------------------------------
 // pass 1
@@ -57,9 +60,9 @@ __device__ __forceinline__ void stage_point(const AsmArgs& a, int64_t e, int q, 
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
-          for (int n = 0; n < 3; ++n) rec[27 * i + 9 * m + 3 * k + n] = hat_entry(h, i, m, k, n);
+          for (int n = 0; n < 3; ++n) rec[kRowA * i + 9 * m + 3 * k + n] = hat_entry(h, i, m, k, n);
 #pragma unroll
-    for (int t = 0; t < 9; ++t) rec[81 + t] = h.P[t];
+    for (int t = 0; t < 9; ++t) rec[kOffP + 4 * (t / 3) + t % 3] = h.P[t];
   } else {
 #pragma unroll
     for (int t = 0; t < 9; ++t) rec[4 * (t / 3) + t % 3] = h.P[t];
@@ -94,6 +97,35 @@ __global__ __launch_bounds__(256) void k_stage_batch(BatchArgs b) {
 // ---------------------------------------------------------------------------
 // pass 2
 // ---------------------------------------------------------------------------
+template <typename R, bool WANT_K>
+struct RowBuf {
+  R a[WANT_K ? kRowA : 4];  // Ahat row (27 used)
+  R p[4];                    // Phat row (3 used)
+};
+
+template <typename T>
+struct Vec4 { using type = float4; };
+template <>
+struct Vec4<double> { using type = double2; };
+
+// one record row with 16-byte vector loads
+template <typename R, bool WANT_K>
+__device__ __forceinline__ void load_row(const R* rec, int i, RowBuf<R, WANT_K>& b) {
+  using V = typename Vec4<R>::type;
+  constexpr int per = sizeof(V) / sizeof(R);
+  if constexpr (WANT_K) {
+    const V* src = reinterpret_cast<const V*>(rec + kRowA * i);
+#pragma unroll
+    for (int t = 0; t < kRowA / per; ++t) *reinterpret_cast<V*>(b.a + per * t) = src[t];
+    const V* sp = reinterpret_cast<const V*>(rec + kOffP + 4 * i);
+#pragma unroll
+    for (int t = 0; t < 4 / per; ++t) *reinterpret_cast<V*>(b.p + per * t) = sp[t];
+  } else {
+    const V* sp = reinterpret_cast<const V*>(rec + 4 * i);
+#pragma unroll
+    for (int t = 0; t < 4 / per; ++t) *reinterpret_cast<V*>(b.p + per * t) = sp[t];
+  }
+}
 template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM>
 __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, int32_t I1, double* lds,
                                              int32_t* pre) {
@@ -109,19 +141,18 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   const int nrow = (int)(row1 - row0);
   double* lf = lds + nseg;
   for (int t = tid; t < nseg + nrow; t += nthr) lds[t] = 0.0;
-  if (tid == 0) {
-    int acc = 0;
-    for (int n = 0; n < nn; ++n) {
-      pre[n] = acc;
-      acc += TPI * (g.inc_off[I0 + n + 1] - g.inc_off[I0 + n]);
-    }
-    pre[nn] = acc;
-  }
+  // the incidence offsets are already a prefix sum: task offsets of the
+  // range's nodes follow from one parallel load
+  const int32_t inc0 = g.inc_off[I0];
+  for (int n = tid; n <= nn; n += nthr) pre[n] = TPI * (g.inc_off[I0 + n] - inc0);
   __syncthreads();
   const int ntask = pre[nn];
   for (int t = tid; t < ntask; t += nthr) {
-    int n = 0;
-    while (pre[n + 1] <= t) ++n;
+    int n = 0, hi = nn - 1;  // last node whose first task is <= t
+    while (n < hi) {
+      const int mid = (n + hi + 1) >> 1;
+      if (pre[mid] <= t) n = mid; else hi = mid - 1;
+    }
     const int64_t I = I0 + n;
     const int tau = t - pre[n], j = tau / TPI, r = tau % TPI, c = r / 3, i = r % 3;
     const int32_t packed = g.inc[g.inc_off[I] + j];
@@ -140,17 +171,18 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
     for (int b = 0; b < NB; ++b) acc[b][0] = acc[b][1] = acc[b][2] = R(0);
     R facc = R(0);
     const R* recs = (const R*)g.stage + e * NQ * REC;
+    // two-stage pipeline over the points: the row of point q + 1 is in flight
+    // while point q is contracted
+    RowBuf<R, WANT_K> cur, nxt;
+    load_row<R, WANT_K>(recs, i, cur);
     sfor<0, NQ>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      const R* rec = recs + q * REC;
+      if constexpr (q + 1 < NQ) load_row<R, WANT_K>(recs + (q + 1) * REC, i, nxt);
       const R d0 = (R)Rule::dN_rt(q, al, 0) * sc_al, d1 = (R)Rule::dN_rt(q, al, 1) * sc_al,
               d2 = (R)Rule::dN_rt(q, al, 2) * sc_al;
-      if constexpr (WANT_F) {
-        const R* Pr = WANT_K ? rec + 81 + 3 * i : rec + 4 * i;
-        facc += Pr[0] * d0 + Pr[1] * d1 + Pr[2] * d2;
-      }
+      if constexpr (WANT_F) facc += cur.p[0] * d0 + cur.p[1] * d1 + cur.p[2] * d2;
       if constexpr (WANT_K) {
-        const R* Ar = rec + 27 * i;
+        const R* Ar = cur.a;
         R tk[3][3];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
@@ -170,6 +202,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
           }
         });
       }
+      if constexpr (q + 1 < NQ) cur = nxt;
     });
     const int64_t row = (int64_t)TPI * I + 3 * c + i;
     if constexpr (WANT_F) atomicAdd(lf + (row - row0), (double)facc);

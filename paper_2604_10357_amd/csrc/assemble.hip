@@ -12,33 +12,51 @@
 // float64 atomics retire at roughly the rate of random read-modify-writes, so
 // this library never issues them:
 //
-//   pass 1 (k_stage, one lane per element x quadrature point): gather the
-//     element, form F and Fdot in float64, run the constitutive update and
-//     store the point's tangent and stress in parent coordinates with the
-//     quadrature volume folded in,
+//   pass 1 (one lane per element x quadrature point): gather the element,
+//     form F and Fdot in float64, run the constitutive update and store the
+//     point's tangent and stress in parent coordinates with the quadrature
+//     volume folded in,
 //        Ahat_imkn = dV sum_JL J0inv_mJ A_iJkL J0inv_nL,  Phat_im = dV sum_J P_iJ J0inv_mJ,
-//     as one 96-value record: Ahat row i at [28 i, 28 i + 27), Phat row i at
-//     [84 + 4 i, 84 + 4 i + 3), so that every row starts on 16 bytes.
-//   pass 2 (k_gather, one workgroup per contiguous range of nodes): the CSR
-//     rows of consecutive nodes form one contiguous segment, mirrored in LDS.
-//     Each lane owns one (node, incident element, coefficient row) task and
-//     contracts the records of that element,
-//        t_kn = sum_m dN_a,m Ahat_imkn,   K[a i, b k] += sum_n t_kn dN_b,n,
+//     as one record of nine 10-value slots: slot (i, k) holds Ahat_imkn at
+//     3 m + n and Phat_ik at 9 (90 values, padded to 96).
+//   pass 2 (one workgroup per contiguous range of nodes): the CSR rows of
+//     consecutive nodes form one contiguous segment, mirrored in LDS.  Each
+//     lane owns one (node, incident element, coefficient row i, component k)
+//     task, reads slot (i, k) of the element's records at every point and forms
+//        t_n = sum_m dN_a,m Ahat_imkn,   K[a i, b k] += sum_n t_n dN_b,n,
 //     where the parent gradients dN_b at each point are compile-time constants
 //     (zeros skipped).  Results are added into the LDS segment in float64, and
 //     the segment and the node forces are then written with plain coalesced
 //     stores.  f_int comes out of the same pass from Phat.
 //   Workgroups are remapped so each XCD walks a contiguous range of elements /
 //   nodes, keeping the records a range reads in its own L2.
+#include <atomic>
+
 #include "kernel_common.h"
 
 namespace tlfea {
 namespace {
 
-constexpr int kRecK = 96;  // record length with tangent: Ahat rows padded to 28, Phat rows padded to 4
-constexpr int kRecF = 12;  // record length for the force only: Phat rows padded to 4
-constexpr int kRowA = 28;  // Ahat row stride within a record
-constexpr int kOffP = 84;  // Phat offset within a tangent record
+constexpr int kRecK = 96;  // tangent record: nine slots of kSlot values, padded
+constexpr int kSlot = 10;  // slot (i, k): Ahat_imkn at 3 m + n, Phat_ik at 9
+constexpr int kRecF = 12;  // force-only record: Phat_ik at 4 i + k
+
+// 16-byte vectors as native clang vector types (HIP's struct vector types are
+// not always promoted to registers)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+struct Vec4 { using type = f32x4; };
+template <>
+struct Vec4<double> { using type = f64x2; };
+
+// ordering of LDS accesses between the lanes of one wave
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // ---------------------------------------------------------------------------
 // pass 1
@@ -56,13 +74,16 @@ __device__ __forceinline__ void stage_point(const AsmArgs& a, int64_t e, int q, 
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int m = 0; m < 3; ++m)
+      for (int k = 0; k < 3; ++k) {
+        R* slot = rec + kSlot * (3 * i + k);
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+        for (int m = 0; m < 3; ++m)
 #pragma unroll
-          for (int n = 0; n < 3; ++n) rec[kRowA * i + 9 * m + 3 * k + n] = hat_entry(h, i, m, k, n);
+          for (int n = 0; n < 3; ++n) slot[3 * m + n] = hat_entry(h, i, m, k, n);
+        slot[9] = h.P[3 * i + k];
+      }
 #pragma unroll
-    for (int t = 0; t < 9; ++t) rec[kOffP + 4 * (t / 3) + t % 3] = h.P[t];
+    for (int t = 9 * kSlot; t < kRecK; ++t) rec[t] = R(0);
   } else {
 #pragma unroll
     for (int t = 0; t < 9; ++t) rec[4 * (t / 3) + t % 3] = h.P[t];
@@ -77,171 +98,440 @@ __global__ __launch_bounds__(256) void k_stage(AsmArgs a, R* stage) {
   stage_point<Rule, R, WANT_K>(a, p / NQ, (int)(p % NQ), stage + p * (WANT_K ? kRecK : kRecF));
 }
 
-// many bodies: the flat (element, point) index is resolved to a body by bisection
+// Value W of a tangent record (W is a compile-time index into the layout above).
+template <int W, typename R>
+__device__ __forceinline__ R record_value(const HatOut<R>& h) {
+  if constexpr (W < 9 * kSlot) {
+    constexpr int slot = W / kSlot, x = W % kSlot, i = slot / 3, k = slot % 3;
+    if constexpr (x < 9) return hat_entry(h, i, x / 3, k, x % 3);
+    else return h.P[3 * i + k];
+  } else {
+    return R(0);
+  }
+}
+
+// Pass 1 with the tangent, one workgroup per 256 consecutive (element, point)
+// indices.  The nodal values of the workgroup's elements (u = q - X and qdot
+// per coefficient) are gathered into LDS once instead of once per point, and
+// the records leave through a per-wave LDS transpose: each 128-byte piece of
+// the wave's 64 records is one cache line, stored by 8 lanes with 16-byte
+// writes, so every store instruction writes 8 whole lines.
+template <class Rule>
+constexpr int stage_elems() { return (kStageThreads - 1) / Rule::NQ + 2; }
+
 template <class Rule, typename R>
-__global__ __launch_bounds__(256) void k_stage_batch(BatchArgs b) {
-  constexpr int NQ = Rule::NQ;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= b.n_points) return;
+constexpr size_t stage_lds_bytes() {
+  const size_t nodal = (size_t)stage_elems<Rule>() * Rule::NEN * 6 * sizeof(double);
+  const size_t trans = (size_t)kStageThreads * (128 + 16);
+  return nodal > trans ? nodal : trans;
+}
+
+template <class Rule, typename R>
+__device__ __forceinline__ void stage_tile(const AsmArgs& a, R* stage, int64_t blk) {
+  constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN;
+  constexpr int EB = stage_elems<Rule>();
+  using V = typename Vec4<R>::type;
+  constexpr int PER = (int)(sizeof(V) / sizeof(R));
+  __shared__ __align__(16) unsigned char smem[stage_lds_bytes<Rule, R>()];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t npts = a.n_elem * NQ;
+  const int64_t p0 = blk * kStageThreads;
+  const int64_t e_lo = p0 / NQ;
+  const int64_t p = p0 + tid;
+  const bool act = p < npts;
+  // 1. nodal values of the elements the block's points belong to
+  double* nod = reinterpret_cast<double*>(smem);
+  for (int idx = tid; idx < EB * NEN; idx += kStageThreads) {
+    const int le = idx / NEN, al = idx - le * NEN;
+    const int64_t e = e_lo + le;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (e < a.n_elem) {
+      const int64_t c = coef_of<Rule>(a.conn + e * NPN, al);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) v[i] = a.q[3 * c + i] - a.X[3 * c + i];
+      if (a.qdot) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) v[3 + i] = a.qdot[3 * c + i];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 6; ++t) nod[6 * idx + t] = v[t];
+  }
+  __syncthreads();
+  // 2. kinematics at the lane's point (lanes past the end evaluate the last
+  //    point and store nothing)
+  const int64_t pc = act ? p : npts - 1;
+  const int64_t e = pc / NQ;
+  const int q = (int)(pc - e * NQ);
+  const double* ne = nod + 6 * NEN * (int)(e - e_lo);
+  double Jinv[9], det, sc[4];
+  load_geometry<Rule>(a, e, q, Jinv, det);
+  element_scales<Rule>(a, e, sc);
+  double Du[9], Dv[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) Du[t] = Dv[t] = 0.0;
+#pragma unroll
+  for (int al = 0; al < NEN; ++al) {
+    const double s = sc[al % 4];
+    const double w0 = Rule::dN_rt(q, al, 0) * s, w1 = Rule::dN_rt(q, al, 1) * s, w2 = Rule::dN_rt(q, al, 2) * s;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double u = ne[6 * al + i], v = ne[6 * al + 3 + i];
+      Du[3 * i] += u * w0;
+      Du[3 * i + 1] += u * w1;
+      Du[3 * i + 2] += u * w2;
+      Dv[3 * i] += v * w0;
+      Dv[3 * i + 1] += v * w1;
+      Dv[3 * i + 2] += v * w2;
+    }
+  }
+  double Hd[9], Fd[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      Hd[3 * i + J] = Du[3 * i] * Jinv[J] + Du[3 * i + 1] * Jinv[3 + J] + Du[3 * i + 2] * Jinv[6 + J];
+      Fd[3 * i + J] = Dv[3 * i] * Jinv[J] + Dv[3 * i + 1] * Jinv[3 + J] + Dv[3 * i + 2] * Jinv[6 + J];
+    }
+  __syncthreads();  // the nodal values are consumed: the LDS becomes the transpose buffers
+  PointOut<R> o;
+  const unsigned fl = point_update<R, true>(a.mp, Hd, Fd, det * Rule::w_rt(q), a.alpha, a.beta, o);
+  if (act && fl) atomicOr(a.flags, fl);
+  HatOut<R> h;
+  to_parent<R, true>(o, Jinv, h);
+  // 3. records through the per-wave transpose, one 128-byte piece at a time
+  constexpr int CW = 128 / (int)sizeof(R);       // values per piece
+  constexpr int LS = CW + 16 / (int)sizeof(R);   // lane stride in the buffer (padded)
+  R* tb = reinterpret_cast<R*>(smem) + wave * 64 * LS;
+  const int64_t pw = p0 + 64 * wave;
+  sfor<0, kRecK / CW>([&](auto cc) __attribute__((always_inline)) {
+    constexpr int ch = decltype(cc)::value;
+    wave_sync();
+    sfor<0, CW / PER>([&](auto jc) __attribute__((always_inline)) {
+      constexpr int j = decltype(jc)::value;
+      V v;
+      sfor<0, PER>([&](auto xc) __attribute__((always_inline)) {
+        constexpr int x = decltype(xc)::value;
+        v[x] = record_value<ch * CW + j * PER + x>(h);
+      });
+      *reinterpret_cast<V*>(tb + lane * LS + j * PER) = v;
+    });
+    wave_sync();
+#pragma unroll
+    for (int s8 = 0; s8 < 8; ++s8) {
+      const int r = 8 * s8 + (lane >> 3), j = lane & 7;
+      if (pw + r < npts)
+        *reinterpret_cast<V*>(stage + (pw + r) * kRecK + ch * CW + j * PER) =
+            *reinterpret_cast<const V*>(tb + r * LS + j * PER);
+    }
+  });
+}
+
+template <class Rule, typename R>
+__global__ __launch_bounds__(kStageThreads) void k_stage_tile(AsmArgs a, R* stage) {
+  stage_tile<Rule, R>(a, stage, blockIdx.x);
+}
+
+// many bodies: every body starts on a block of its own, found by bisection
+template <class Rule, typename R>
+__global__ __launch_bounds__(kStageThreads) void k_stage_batch(BatchArgs b) {
+  const int64_t blk = blockIdx.x;
   int lo = 0, hi = b.n_bodies - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (b.bodies[mid].point_off <= p) lo = mid; else hi = mid - 1;
+    if (b.bodies[mid].block_off <= blk) lo = mid; else hi = mid - 1;
   }
   const BatchBody& B = b.bodies[lo];
   const AsmArgs a = body_args(b, B, lo);
-  const int64_t lp = p - B.point_off;
-  stage_point<Rule, R, true>(a, lp / NQ, (int)(lp % NQ), (R*)b.stage + p * kRecK);
+  stage_tile<Rule, R>(a, (R*)b.stage + B.point_off * kRecK, blk - B.block_off);
 }
 
 // ---------------------------------------------------------------------------
 // pass 2
 // ---------------------------------------------------------------------------
+// Values one lane reads per point: its slot of a tangent record, or its Phat
+// entry of a force record.
 template <typename R, bool WANT_K>
-struct RowBuf {
-  R a[WANT_K ? kRowA : 4];  // Ahat row (27 used)
-  R p[4];                    // Phat row (3 used)
+struct Slot {
+  static constexpr int N = WANT_K ? kSlot : 1;
+  R v[N];
 };
 
-template <typename T>
-struct Vec4 { using type = float4; };
-template <>
-struct Vec4<double> { using type = double2; };
-
-// one record row with 16-byte vector loads
+// read a slot from the wave's LDS copy of the records (8-byte aligned for
+// float, 16-byte aligned for double)
 template <typename R, bool WANT_K>
-__device__ __forceinline__ void load_row(const R* rec, int i, RowBuf<R, WANT_K>& b) {
-  using V = typename Vec4<R>::type;
-  constexpr int per = sizeof(V) / sizeof(R);
-  if constexpr (WANT_K) {
-    const V* src = reinterpret_cast<const V*>(rec + kRowA * i);
+__device__ __forceinline__ void load_slot(const R* p, Slot<R, WANT_K>& s) {
+  if constexpr (!WANT_K) {
+    s.v[0] = *p;
+  } else if constexpr (sizeof(R) == 8) {
 #pragma unroll
-    for (int t = 0; t < kRowA / per; ++t) *reinterpret_cast<V*>(b.a + per * t) = src[t];
-    const V* sp = reinterpret_cast<const V*>(rec + kOffP + 4 * i);
-#pragma unroll
-    for (int t = 0; t < 4 / per; ++t) *reinterpret_cast<V*>(b.p + per * t) = sp[t];
+    for (int t = 0; t < kSlot / 2; ++t) {
+      const f64x2 x = reinterpret_cast<const f64x2*>(p)[t];
+      s.v[2 * t] = x[0];
+      s.v[2 * t + 1] = x[1];
+    }
   } else {
-    const V* sp = reinterpret_cast<const V*>(rec + 4 * i);
 #pragma unroll
-    for (int t = 0; t < 4 / per; ++t) *reinterpret_cast<V*>(b.p + per * t) = sp[t];
+    for (int t = 0; t < kSlot / 2; ++t) {
+      const f32x2 x = reinterpret_cast<const f32x2*>(p)[t];
+      s.v[2 * t] = x[0];
+      s.v[2 * t + 1] = x[1];
+    }
   }
 }
+
+// One point's contribution of a task (row i, component k of node a's
+// coefficient al): with the slot of the task's element at point Q and the
+// task's scaled parent gradient d,
+//   t_n = sum_m d_m Ahat_imkn,  acc[b] += sum_n t_n dN_b,n(Q),  facc += Phat_ik d_k.
+template <class Rule, typename R, bool WANT_F, bool WANT_K, int Q, int NB>
+__device__ __forceinline__ void contract_point(const Slot<R, WANT_K>& s, int al, int k, R sc_al, R (&acc)[NB],
+                                               R& facc) {
+  const R d0 = (R)Rule::dN_rt(Q, al, 0) * sc_al, d1 = (R)Rule::dN_rt(Q, al, 1) * sc_al,
+          d2 = (R)Rule::dN_rt(Q, al, 2) * sc_al;
+  if constexpr (WANT_F) facc += (WANT_K ? s.v[9] : s.v[0]) * (k == 0 ? d0 : k == 1 ? d1 : d2);
+  if constexpr (WANT_K) {
+    R tn[3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) tn[n] = s.v[n] * d0 + s.v[3 + n] * d1 + s.v[6 + n] * d2;
+    sfor<0, Rule::NEN>([&](auto bc) __attribute__((always_inline)) {
+      constexpr int b = decltype(bc)::value;
+      constexpr double c0 = Rule::dN(Q, b, 0), c1 = Rule::dN(Q, b, 1), c2 = Rule::dN(Q, b, 2);
+      R v = acc[b];
+      if constexpr (c0 != 0.0) v += tn[0] * R(c0);
+      if constexpr (c1 != 0.0) v += tn[1] * R(c1);
+      if constexpr (c2 != 0.0) v += tn[2] * R(c2);
+      acc[b] = v;
+    });
+  }
+}
+
+// Pass-2 records travel through LDS: the 64 tasks of a wave touch at most
+// chunk_incidences() consecutive incidences, whose records are copied, one
+// point at a time, into a wave-private LDS buffer with 16-byte loads of
+// consecutive lanes (whole cache lines per instruction); each lane then reads
+// its own slot from there.  The copies of the next points are in flight in
+// registers while a point is contracted.
+constexpr int chunk_incidences(int tpi) { return (tpi + 62) / tpi + 1; }
+
+template <class Rule, typename R, bool WANT_K>
+constexpr size_t wave_buf_bytes() {
+  return (size_t)chunk_incidences(9 * Rule::MC) * (WANT_K ? kRecK : kRecF) * sizeof(R);
+}
+
+// The same with a run-time point index q (long rules); q is uniform across the
+// wave, so the gradients dN_b(q) come through the scalar cache.
+template <class Rule, typename R, bool WANT_F, bool WANT_K, int NB>
+__device__ __forceinline__ void contract_point_rt(const Slot<R, WANT_K>& s, int q, int al, int k, R sc_al,
+                                                  R (&acc)[NB], R& facc) {
+  const R d0 = (R)Rule::dN_rt(q, al, 0) * sc_al, d1 = (R)Rule::dN_rt(q, al, 1) * sc_al,
+          d2 = (R)Rule::dN_rt(q, al, 2) * sc_al;
+  if constexpr (WANT_F) facc += (WANT_K ? s.v[9] : s.v[0]) * (k == 0 ? d0 : k == 1 ? d1 : d2);
+  if constexpr (WANT_K) {
+    R tn[3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) tn[n] = s.v[n] * d0 + s.v[3 + n] * d1 + s.v[6 + n] * d2;
+#pragma unroll
+    for (int b = 0; b < Rule::NEN; ++b)
+      acc[b] += tn[0] * (R)Rule::dN_rt(q, b, 0) + tn[1] * (R)Rule::dN_rt(q, b, 1) + tn[2] * (R)Rule::dN_rt(q, b, 2);
+  }
+}
+
 template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM>
-__device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, int32_t I1, double* lds,
-                                             int32_t* pre) {
-  constexpr int NEN = Rule::NEN, NQ = Rule::NQ, NPN = Rule::NPN, MC = Rule::MC;
-  constexpr int TPI = 3 * MC;  // tasks (coefficient rows) per incidence
+__device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, int32_t I1, unsigned char* smem,
+                                             int32_t* pre, int32_t* rowo) {
+  constexpr int NQ = Rule::NQ, NPN = Rule::NPN, MC = Rule::MC, NEN = Rule::NEN;
+  constexpr int RPN = 3 * MC;  // CSR rows per node
+  constexpr int TPI = 3 * RPN; // tasks per incidence: (coefficient kind, row, component)
   constexpr int REC = WANT_K ? kRecK : kRecF;
+  constexpr int NI = chunk_incidences(TPI);
+  using V = typename Vec4<R>::type;
+  constexpr int PER = (int)(sizeof(V) / sizeof(R));
+  constexpr int NV = REC / PER;            // 16-byte pieces per record
+  constexpr int KC = (NI * NV + 63) / 64;  // pieces each lane copies per point
+  // short rules are unrolled over all points (gradients dN_b as compile-time
+  // constants); long rules run over blocks of PB points
+  constexpr bool UNROLL = NQ <= 6;
+  constexpr int PB = UNROLL ? NQ : 3;
+  static_assert(NQ % PB == 0, "point blocks must tile the rule");
+  constexpr int PD = UNROLL ? (sizeof(R) == 4 ? NQ : 3) : PB;  // points whose pieces are in flight
   constexpr int NB = WANT_K ? NEN : 1;
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+  R* wbuf = reinterpret_cast<R*>(smem) + wave * NI * REC;
+  double* lds = reinterpret_cast<double*>(smem + nwave * wave_buf_bytes<Rule, R, WANT_K>());
   const int nn = I1 - I0;
-  const int64_t row0 = (int64_t)TPI * I0, row1 = (int64_t)TPI * I1;
+  const int64_t row0 = (int64_t)RPN * I0, row1 = (int64_t)RPN * I1;
   const int64_t seg0 = WANT_K ? g.row_off[row0] : 0, seg1 = WANT_K ? g.row_off[row1] : 0;
   const int nseg = (int)(seg1 - seg0);
   const int nrow = (int)(row1 - row0);
   double* lf = lds + nseg;
-  for (int t = tid; t < nseg + nrow; t += nthr) lds[t] = 0.0;
+  for (int t = tid; t < nseg + nrow; t += blockDim.x) lds[t] = 0.0;
   // the incidence offsets are already a prefix sum: task offsets of the
   // range's nodes follow from one parallel load
   const int32_t inc0 = g.inc_off[I0];
-  for (int n = tid; n <= nn; n += nthr) pre[n] = TPI * (g.inc_off[I0 + n] - inc0);
+  for (int n = tid; n <= nn; n += blockDim.x) pre[n] = TPI * (g.inc_off[I0 + n] - inc0);
+  // segment-relative offsets of the range's CSR rows
+  if constexpr (WANT_K)
+    for (int rr = tid; rr < nrow; rr += blockDim.x) rowo[rr] = (int32_t)(g.row_off[row0 + rr] - seg0);
   __syncthreads();
   const int ntask = pre[nn];
-  for (int t = tid; t < ntask; t += nthr) {
+  const R* stage = (const R*)g.stage;
+  // Tasks are ordered (node, incidence, kind, row, component): task t belongs
+  // to incidence inc0 + t / TPI of the range.  The wave's chunk of an
+  // iteration starting at task t0 covers incidences j0 .. j0 + ni - 1; lanes
+  // past the last task repeat it and store nothing, and copy pieces past the
+  // chunk's end repeat its last piece (in bounds, same value written twice).
+  auto chunk = [&](int t0_, int& j0_, int& ni_) __attribute__((always_inline)) {
+    const int cw = min(t0_ + 64 * wave, ntask - 1);
+    j0_ = cw / TPI;
+    ni_ = min(cw + 63, ntask - 1) / TPI - j0_ + 1;
+  };
+  // incidence entries an iteration needs (its copy pieces' and the lane's
+  // own), fetched one iteration ahead
+  auto fetch_inc = [&](int t0_, int32_t (&icp)[KC], int32_t& ime) __attribute__((always_inline)) {
+    int j0_, ni_;
+    chunk(t0_, j0_, ni_);
+#pragma unroll
+    for (int k = 0; k < KC; ++k) icp[k] = g.inc[inc0 + j0_ + min(lane + 64 * k, ni_ * NV - 1) / NV];
+    ime = g.inc[inc0 + min(t0_ + tid, ntask - 1) / TPI];
+  };
+  int32_t icp[KC], ime;
+  fetch_inc(0, icp, ime);
+  for (int t0 = 0; t0 < ntask; t0 += blockDim.x) {  // uniform across the workgroup
+    const bool act = t0 + tid < ntask;
+    const int t = min(t0 + tid, ntask - 1);
+    int j0, ni;
+    chunk(t0, j0, ni);
+    int64_t src[KC];
+    int dst[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int c = min(lane + 64 * k, ni * NV - 1);
+      const int rr = c / NV, pp = c - rr * NV;
+      src[k] = (int64_t)(icp[k] >> 4) * NQ * REC + pp * PER;
+      dst[k] = rr * REC + pp * PER;
+    }
+    V buf[PD][KC];
+    sfor<0, PD>([&](auto qc) __attribute__((always_inline)) {
+      constexpr int q = decltype(qc)::value;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) buf[q][k] = *reinterpret_cast<const V*>(stage + src[k] + q * REC);
+    });
+    const int32_t packed = ime;
+    if (t0 + (int)blockDim.x < ntask) fetch_inc(t0 + blockDim.x, icp, ime);
     int n = 0, hi = nn - 1;  // last node whose first task is <= t
     while (n < hi) {
       const int mid = (n + hi + 1) >> 1;
       if (pre[mid] <= t) n = mid; else hi = mid - 1;
     }
-    const int64_t I = I0 + n;
-    const int tau = t - pre[n], j = tau / TPI, r = tau % TPI, c = r / 3, i = r % 3;
-    const int32_t packed = g.inc[g.inc_off[I] + j];
+    const int r = t % TPI, ca = r / 9, i = (r / 3) % 3, k = r % 3;  // pre[] holds multiples of TPI
     const int64_t e = packed >> 4;
     const int a = packed & 15;
-    const int al = MC * a + c;
+    const int al = MC * a + ca;
+    const R* mine = wbuf + (t / TPI - j0) * REC + (WANT_K ? kSlot * (3 * i + k) : 4 * i + k);
+    // slot-map row of (e, a): one aligned vector load
+    constexpr int RST = rank_stride(NPN);
+    uint32_t rkw[RST / 4];
+    if constexpr (WANT_K) {
+      const uint32_t* rp = reinterpret_cast<const uint32_t*>(g.rank + (e * NPN + a) * RST);
+      if constexpr (RST == 16) {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 w = *reinterpret_cast<const u32x4*>(rp);
+        rkw[0] = w[0];
+        rkw[1] = w[1];
+        rkw[2] = w[2];
+        rkw[3] = w[3];
+      } else {
+        rkw[0] = rp[0];
+      }
+    }
     double scd[4] = {1.0, 1.0, 1.0, 1.0};
     if constexpr (MC == 4) {
       scd[1] = g.escale[2 * e];
       scd[2] = g.escale[2 * e + 1];
       scd[3] = g.half_h;
     }
-    const R sc_al = (R)scd[al % 4];
-    R acc[NB][3];
+    const R sc_al = (R)(ca == 0 ? scd[0] : ca == 1 ? scd[1] : ca == 2 ? scd[2] : scd[3]);
+    R acc[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b][0] = acc[b][1] = acc[b][2] = R(0);
+    for (int b = 0; b < NB; ++b) acc[b] = R(0);
     R facc = R(0);
-    const R* recs = (const R*)g.stage + e * NQ * REC;
-    // two-stage pipeline over the points: the row of point q + 1 is in flight
-    // while point q is contracted
-    RowBuf<R, WANT_K> cur, nxt;
-    load_row<R, WANT_K>(recs, i, cur);
-    sfor<0, NQ>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      if constexpr (q + 1 < NQ) load_row<R, WANT_K>(recs + (q + 1) * REC, i, nxt);
-      const R d0 = (R)Rule::dN_rt(q, al, 0) * sc_al, d1 = (R)Rule::dN_rt(q, al, 1) * sc_al,
-              d2 = (R)Rule::dN_rt(q, al, 2) * sc_al;
-      if constexpr (WANT_F) facc += cur.p[0] * d0 + cur.p[1] * d1 + cur.p[2] * d2;
-      if constexpr (WANT_K) {
-        const R* Ar = cur.a;
-        R tk[3][3];
+    if constexpr (UNROLL) {
+      sfor<0, NQ>([&](auto qc) __attribute__((always_inline)) {
+        constexpr int q = decltype(qc)::value;
+        wave_sync();  // every lane is done with the previous point's records
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+        for (int kk = 0; kk < KC; ++kk) *reinterpret_cast<V*>(wbuf + dst[kk]) = buf[q % PD][kk];
+        wave_sync();
+        if constexpr (q + PD < NQ) {
 #pragma unroll
-          for (int nq = 0; nq < 3; ++nq)
-            tk[k][nq] = Ar[3 * k + nq] * d0 + Ar[9 + 3 * k + nq] * d1 + Ar[18 + 3 * k + nq] * d2;
-        sfor<0, NEN>([&](auto bc) {
-          constexpr int b = decltype(bc)::value;
-          constexpr double c0 = Rule::dN(q, b, 0), c1 = Rule::dN(q, b, 1), c2 = Rule::dN(q, b, 2);
+          for (int kk = 0; kk < KC; ++kk)
+            buf[q % PD][kk] = *reinterpret_cast<const V*>(stage + src[kk] + (q + PD) * REC);
+        }
+        Slot<R, WANT_K> sl;
+        load_slot<R, WANT_K>(mine, sl);
+        contract_point<Rule, R, WANT_F, WANT_K, q, NB>(sl, al, k, sc_al, acc, facc);
+      });
+    } else {
+#pragma unroll 1
+      for (int qb = 0; qb < NQ; qb += PB) {
+        sfor<0, PB>([&](auto xc) __attribute__((always_inline)) {
+          constexpr int x = decltype(xc)::value;
+          const int q = qb + x;
+          wave_sync();
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            R v = acc[b][k];
-            if constexpr (c0 != 0.0) v += tk[k][0] * R(c0);
-            if constexpr (c1 != 0.0) v += tk[k][1] * R(c1);
-            if constexpr (c2 != 0.0) v += tk[k][2] * R(c2);
-            acc[b][k] = v;
+          for (int kk = 0; kk < KC; ++kk) *reinterpret_cast<V*>(wbuf + dst[kk]) = buf[x][kk];
+          wave_sync();
+          if (q + PB < NQ) {
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk)
+              buf[x][kk] = *reinterpret_cast<const V*>(stage + src[kk] + (int64_t)(q + PB) * REC);
           }
+          Slot<R, WANT_K> sl;
+          load_slot<R, WANT_K>(mine, sl);
+          contract_point_rt<Rule, R, WANT_F, WANT_K, NB>(sl, q, al, k, sc_al, acc, facc);
         });
       }
-      if constexpr (q + 1 < NQ) cur = nxt;
-    });
-    const int64_t row = (int64_t)TPI * I + 3 * c + i;
-    if constexpr (WANT_F) atomicAdd(lf + (row - row0), (double)facc);
-    if constexpr (WANT_K) {
-      const int64_t base = g.row_off[row] - seg0;
-      const uint8_t* rk = g.rank + (e * NPN + a) * NPN;
+    }
+    if (act) {
+      const int rl = RPN * n + 3 * ca + i;  // row within the range
+      if constexpr (WANT_F) atomicAdd(lf + rl, (double)facc);
+      if constexpr (WANT_K) {
+        double* dstp = lds + rowo[rl] + k;
 #pragma unroll
-      for (int b = 0; b < NEN; ++b) {
-        const int pb = (MC == 1) ? b : (b >> 2), cb = (MC == 1) ? 0 : (b & 3);
-        double* dst = lds + base + 3 * (MC * (int)rk[pb] + cb);
-        const double sb = scd[b % 4];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) atomicAdd(dst + k, (double)acc[b][k] * sb);
+        for (int b = 0; b < NEN; ++b) {
+          const int pb = (MC == 1) ? b : (b >> 2), cb = (MC == 1) ? 0 : (b & 3);
+          const int rank_b = (int)((rkw[pb >> 2] >> (8 * (pb & 3))) & 255u);
+          atomicAdd(dstp + 3 * (MC * rank_b + cb), (double)acc[b] * scd[b % 4]);
+        }
       }
     }
   }
   __syncthreads();
   if constexpr (WANT_K) {
     double* out = g.vals + seg0;
-    for (int t = tid; t < nseg; t += nthr) out[t] = ACCUM ? out[t] + lds[t] : lds[t];
+    for (int t = tid; t < nseg; t += blockDim.x) out[t] = ACCUM ? out[t] + lds[t] : lds[t];
   }
   if constexpr (WANT_F) {
     double* out = g.f + row0;
-    for (int t = tid; t < nrow; t += nthr) out[t] = ACCUM ? out[t] + lf[t] : lf[t];
+    for (int t = tid; t < nrow; t += blockDim.x) out[t] = ACCUM ? out[t] + lf[t] : lf[t];
   }
 }
 
 template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs g) {
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t pre[kMaxRangeNodes + 1];
+  __shared__ int32_t rowo[kMaxRangeNodes * 3 * Rule::MC];
   const int r = remap_tile(blockIdx.x, gridDim.x);
-  gather_range<Rule, R, WANT_F, WANT_K, ACCUM>(g, g.ranges[r], g.ranges[r + 1], lds, pre);
+  gather_range<Rule, R, WANT_F, WANT_K, ACCUM>(g, g.ranges[r], g.ranges[r + 1], smem, pre, rowo);
 }
 
 template <class Rule, typename R>
 __global__ __launch_bounds__(256) void k_gather_batch(BatchArgs b) {
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t pre[kMaxRangeNodes + 1];
+  __shared__ int32_t rowo[kMaxRangeNodes * 3 * Rule::MC];
   const int r = remap_tile(blockIdx.x, gridDim.x);
   const BatchRange br = b.ranges[r];
   const BatchBody& B = b.bodies[br.body];
@@ -256,13 +546,29 @@ __global__ __launch_bounds__(256) void k_gather_batch(BatchArgs b) {
   g.stage = (const R*)b.stage + B.point_off * kRecK;
   g.f = b.f + B.dof_off;
   g.vals = b.vals + B.nnz_off;
-  gather_range<Rule, R, true, true, false>(g, br.I0, br.I1, lds, pre);
+  gather_range<Rule, R, true, true, false>(g, br.I0, br.I1, smem, pre, rowo);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 int grid_of(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+// Dynamic LDS beyond 64 KiB has to be allowed per kernel; the largest size
+// granted so far is remembered per kernel instantiation.
+template <typename Kernel>
+int allow_lds(Kernel* kernel, size_t bytes) {
+  static std::atomic<size_t> granted{64 * 1024};
+  if (bytes <= granted.load(std::memory_order_relaxed)) return TLFEA_OK;
+  int dev = 0, max_bytes = 0;
+  TLFEA_HIP_CHECK(hipGetDevice(&dev));
+  TLFEA_HIP_CHECK(hipDeviceGetAttribute(&max_bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if (bytes > (size_t)max_bytes) return TLFEA_ERR_UNSUPPORTED;
+  TLFEA_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  granted.store(bytes, std::memory_order_relaxed);
+  return TLFEA_OK;
+}
 
 template <class Rule, typename R>
 int launch_points_rule(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s) {
@@ -271,7 +577,8 @@ int launch_points_rule(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t
   if (npts == 0) return TLFEA_OK;
   R* stage = (R*)m.d_stage;
   if (want_k)
-    hipLaunchKernelGGL((k_stage<Rule, R, true>), dim3(grid_of(npts, 256)), dim3(256), 0, s, a, stage);
+    hipLaunchKernelGGL((k_stage_tile<Rule, R>), dim3(grid_of(npts, kStageThreads)), dim3(kStageThreads), 0, s, a,
+                       stage);
   else
     hipLaunchKernelGGL((k_stage<Rule, R, false>), dim3(grid_of(npts, 256)), dim3(256), 0, s, a, stage);
   TLFEA_HIP_CHECK(hipGetLastError());
@@ -293,9 +600,14 @@ int launch_nodes_rule(const Mesh& m, double* f, double* vals, bool accum, hipStr
   g.stage = stage;
   g.f = f;
   g.vals = vals;
-  const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows);
-  const dim3 grid((unsigned)m.n_ranges), blk(256);
-#define TLFEA_GATHER(F, K, A) hipLaunchKernelGGL((k_gather<Rule, R, F, K, A>), grid, blk, lds, s, g)
+  const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows) +
+                     (size_t)m.tune.waves * (want_k ? wave_buf_bytes<Rule, R, true>() : wave_buf_bytes<Rule, R, false>());
+  const dim3 grid((unsigned)m.n_ranges), blk(64 * m.tune.waves);
+#define TLFEA_GATHER(F, K, A)                                                \
+  do {                                                                       \
+    if (int rc = allow_lds(k_gather<Rule, R, F, K, A>, lds)) return rc;      \
+    hipLaunchKernelGGL((k_gather<Rule, R, F, K, A>), grid, blk, lds, s, g); \
+  } while (0)
   if (want_k && want_f) {
     if (accum) TLFEA_GATHER(true, true, true); else TLFEA_GATHER(true, true, false);
   } else if (want_k) {
@@ -323,10 +635,13 @@ int launch_nodes_prec(const Mesh& m, double* f, double* vals, bool accum, hipStr
 }
 
 template <class Rule, typename R>
-int launch_batch_rule(const BatchArgs& b, int n_ranges, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_stage_batch<Rule, R>), dim3(grid_of(b.n_points, 256)), dim3(256), 0, s, b);
+int launch_batch_rule(const GatherTuning& tu, const BatchArgs& b, int n_ranges, size_t lds, hipStream_t s) {
+  if (b.n_blocks > 0)
+    hipLaunchKernelGGL((k_stage_batch<Rule, R>), dim3((unsigned)b.n_blocks), dim3(kStageThreads), 0, s, b);
   TLFEA_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL((k_gather_batch<Rule, R>), dim3(n_ranges), dim3(256), lds, s, b);
+  const size_t lds_all = lds + (size_t)tu.waves * wave_buf_bytes<Rule, R, true>();
+  if (int rc = allow_lds(k_gather_batch<Rule, R>, lds_all)) return rc;
+  hipLaunchKernelGGL((k_gather_batch<Rule, R>), dim3(n_ranges), dim3(64 * tu.waves), lds_all, s, b);
   TLFEA_HIP_CHECK(hipGetLastError());
   return TLFEA_OK;
 }
@@ -371,18 +686,18 @@ int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t
   return launch_nodes_prec<double>(m, f, vals, accum, s);
 }
 
-int launch_batch(int elem_type, int gl0, int precision, const BatchArgs& b, int n_ranges, size_t lds,
-                 hipStream_t s) {
+int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tu, const BatchArgs& b,
+                 int n_ranges, size_t lds, hipStream_t s) {
   if (n_ranges == 0) return TLFEA_OK;
   const bool mixed = precision == TLFEA_MIXED;
   if (elem_type == TLFEA_T10)
-    return mixed ? launch_batch_rule<RuleT10, float>(b, n_ranges, lds, s)
-                 : launch_batch_rule<RuleT10, double>(b, n_ranges, lds, s);
+    return mixed ? launch_batch_rule<RuleT10, float>(tu, b, n_ranges, lds, s)
+                 : launch_batch_rule<RuleT10, double>(tu, b, n_ranges, lds, s);
   if (gl0 == 3)
-    return mixed ? launch_batch_rule<RuleAncf<3, 3, 2>, float>(b, n_ranges, lds, s)
-                 : launch_batch_rule<RuleAncf<3, 3, 2>, double>(b, n_ranges, lds, s);
-  return mixed ? launch_batch_rule<RuleAncf<4, 4, 3>, float>(b, n_ranges, lds, s)
-               : launch_batch_rule<RuleAncf<4, 4, 3>, double>(b, n_ranges, lds, s);
+    return mixed ? launch_batch_rule<RuleAncf<3, 3, 2>, float>(tu, b, n_ranges, lds, s)
+                 : launch_batch_rule<RuleAncf<3, 3, 2>, double>(tu, b, n_ranges, lds, s);
+  return mixed ? launch_batch_rule<RuleAncf<4, 4, 3>, float>(tu, b, n_ranges, lds, s)
+               : launch_batch_rule<RuleAncf<4, 4, 3>, double>(tu, b, n_ranges, lds, s);
 }
 
 }  // namespace tlfea

@@ -26,7 +26,7 @@ struct tlfea_batch_s {
   BatchBody* d_bodies = nullptr;
   BatchRange* d_ranges = nullptr;
   int n_ranges = 0;
-  int64_t n_points = 0;
+  int64_t n_points = 0, n_blocks = 0;
   size_t lds = 0;
   void* d_stage = nullptr;
   uint32_t* d_flags = nullptr;
@@ -66,7 +66,8 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
   int64_t max_vals = 0;
   for (int i = 0; i < n_bodies; ++i) {
     const tlfea::Mesh& m = meshes[i]->m;
-    if (m.elem_type != b->elem_type || m.gl[0] != b->gl0 || m.precision != b->precision || m.device != b->device) {
+    if (m.elem_type != b->elem_type || m.gl[0] != b->gl0 || m.precision != b->precision || m.device != b->device ||
+        m.tune.waves != m0.tune.waves) {
       delete b;
       return TLFEA_ERR_INVALID;
     }
@@ -83,17 +84,19 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
     B.dof_off = b->dof_off[i];
     B.nnz_off = b->nnz_off[i];
     B.point_off = b->n_points;
+    B.block_off = b->n_blocks;
     B.affine = m.affine ? 1 : 0;
     B.half_h = 0.5 * m.thickness;
     B.mp = m.mp;
     b->dof_off[i + 1] = b->dof_off[i] + m.n_dof;
     b->nnz_off[i + 1] = b->nnz_off[i] + m.nnz;
     b->n_points += m.n_elem * m.n_qp;
+    b->n_blocks += (m.n_elem * m.n_qp + tlfea::kStageThreads - 1) / tlfea::kStageThreads;
     for (int r = 0; r < m.n_ranges; ++r) ranges.push_back(BatchRange{i, m.h_ranges[r], m.h_ranges[r + 1]});
     max_vals = std::max(max_vals, m.max_range_values);
     b->meshes.push_back(meshes[i]);
   }
-  if (ranges.size() > (size_t)INT32_MAX) { delete b; return TLFEA_ERR_TOO_LARGE; }
+  if (ranges.size() > (size_t)INT32_MAX || b->n_blocks > INT32_MAX) { delete b; return TLFEA_ERR_TOO_LARGE; }
   b->n_ranges = (int)ranges.size();
   b->lds = sizeof(double) * (size_t)max_vals;
   const size_t stage = (size_t)b->n_points * tlfea::stage_record_bytes(b->precision);
@@ -133,7 +136,7 @@ TLFEA_API int tlfea_batch_offsets(tlfea_batch_t batch, int64_t* dof_off, int64_t
 }
 
 static int batch_enqueue(tlfea_batch_t b, const BatchArgs& a, hipStream_t s) {
-  return tlfea::launch_batch(b->elem_type, b->gl0, b->precision, a, b->n_ranges, b->lds, s);
+  return tlfea::launch_batch(b->elem_type, b->gl0, b->precision, b->meshes[0]->m.tune, a, b->n_ranges, b->lds, s);
 }
 
 TLFEA_API int tlfea_batch_assemble(tlfea_batch_t b, const double* d_q, const double* d_qdot, const double* d_h,
@@ -145,6 +148,7 @@ TLFEA_API int tlfea_batch_assemble(tlfea_batch_t b, const double* d_q, const dou
   a.ranges = b->d_ranges;
   a.n_bodies = (int)b->meshes.size();
   a.n_points = b->n_points;
+  a.n_blocks = b->n_blocks;
   a.stage = b->d_stage;
   a.q = d_q;
   a.qdot = d_qdot;

@@ -15,6 +15,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "tlfea_internal.h"
@@ -140,7 +141,8 @@ __global__ __launch_bounds__(64) void k_cols(const int32_t* adj_off, const int32
   }
 }
 
-// rank[e][p][p'] = position of node conn[e][p'] in the sorted adjacency of conn[e][p]
+// rank[e][p][p'] = position of node conn[e][p'] in the sorted adjacency of
+// conn[e][p]; rows of rank_stride(npn) bytes
 __global__ void k_rank(const int32_t* conn, int64_t n_elem, int npn, const int32_t* adj_off,
                        const int32_t* adj, uint8_t* rank, uint32_t* err) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -149,6 +151,7 @@ __global__ void k_rank(const int32_t* conn, int64_t n_elem, int npn, const int32
   const int64_t e = t / (npn * npn);
   const int p = (int)((t / npn) % npn), pb = (int)(t % npn);
   const int32_t a = conn[e * npn + p], b = conn[e * npn + pb];
+  uint8_t* out = rank + (e * npn + p) * rank_stride(npn) + pb;
   int lo = adj_off[a], hi = adj_off[a + 1] - 1;
   int found = -1;
   while (lo <= hi) {
@@ -160,9 +163,9 @@ __global__ void k_rank(const int32_t* conn, int64_t n_elem, int npn, const int32
   const int r = found - adj_off[a];
   if (found < 0 || r > 255) {
     atomicOr(err, 2u);
-    rank[t] = 0;
+    *out = 0;
   } else {
-    rank[t] = (uint8_t)r;
+    *out = (uint8_t)r;
   }
 }
 
@@ -179,7 +182,7 @@ __global__ void k_slots(const int32_t* conn, int64_t e0, int64_t ne, int npn, in
   const int pa = al / mc, ca = al % mc, pb = be / mc, cb = be % mc;
   const int64_t coef_a = (int64_t)mc * conn[e * npn + pa] + ca;
   const int64_t base = row_off[3 * coef_a + i];
-  out[t] = (int32_t)(base + 3 * (mc * (int64_t)rank[(e * npn + pa) * npn + pb] + cb) + k);
+  out[t] = (int32_t)(base + 3 * (mc * (int64_t)rank[(e * npn + pa) * rank_stride(npn) + pb] + cb) + k);
 }
 
 int grid_of(int64_t n, int block) { return (int)((n + block - 1) / block); }
@@ -279,7 +282,7 @@ int build_pattern(Mesh& m) {
   uint8_t* d_rank = nullptr;
   if (hipMalloc(&d_row_off, sizeof(int32_t) * (m.n_dof + 1)) != hipSuccess ||
       hipMalloc(&d_cols, sizeof(int32_t) * (nnz > 0 ? nnz : 1)) != hipSuccess ||
-      hipMalloc(&d_rank, (size_t)(m.n_elem * npn * npn > 0 ? m.n_elem * npn * npn : 1)) != hipSuccess) {
+      hipMalloc(&d_rank, (size_t)(m.n_elem > 0 ? m.n_elem * npn * rank_stride(npn) : 1)) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(d_row_off); (void)hipFree(d_cols); (void)hipFree(d_rank);
     (void)hipFree(d_adj_off); (void)hipFree(d_adj);
@@ -290,6 +293,7 @@ int build_pattern(Mesh& m) {
   if (nn > 0)
     hipLaunchKernelGGL(k_cols, dim3((unsigned)nn), dim3(64), 0, s, d_adj_off, d_adj, d_row_off, nn, mc, d_cols);
   const int64_t nrank = m.n_elem * npn * npn;
+  if (nrank > 0) (void)hipMemsetAsync(d_rank, 0, (size_t)m.n_elem * npn * rank_stride(npn), s);  // padding bytes
   if (nrank > 0)
     hipLaunchKernelGGL(k_rank, dim3(grid_of(nrank, 256)), dim3(256), 0, s, m.d_conn, m.n_elem, npn, d_adj_off,
                        d_adj, d_rank, d_err);
@@ -311,14 +315,15 @@ int build_pattern(Mesh& m) {
   hipError_t e5 = hipMemcpy(h_inc_off.data(), d_inc_off, sizeof(int32_t) * (nn + 1), hipMemcpyDeviceToHost);
   hipError_t e6 = hipMemcpy(h_adj_off.data(), d_adj_off, sizeof(int32_t) * (nn + 1), hipMemcpyDeviceToHost);
   // greedy partition of the nodes into ranges of bounded tasks and LDS values
+  const GatherTuning tune = gather_tuning();
   std::vector<int32_t> ranges{0};
   int64_t max_vals = 0, max_rows = 0;
   {
     int64_t tasks = 0, vals = 0, rows = 0, nodes = 0;
     for (int64_t I = 0; I < nn; ++I) {
-      const int64_t tI = 3LL * mc * (h_inc_off[I + 1] - h_inc_off[I]);
+      const int64_t tI = 9LL * mc * (h_inc_off[I + 1] - h_inc_off[I]);
       const int64_t vI = 9LL * mc * mc * (h_adj_off[I + 1] - h_adj_off[I]) + 3LL * mc;
-      if (nodes > 0 && (tasks + tI > kRangeTasks || vals + vI > kRangeValues || nodes >= kMaxRangeNodes)) {
+      if (nodes > 0 && (tasks + tI > tune.range_tasks || vals + vI > tune.range_values || nodes >= kMaxRangeNodes)) {
         ranges.push_back((int32_t)I);
         max_vals = std::max(max_vals, vals);
         max_rows = std::max(max_rows, rows);
@@ -340,11 +345,12 @@ int build_pattern(Mesh& m) {
   hipError_t e8 = e7 == hipSuccess ? hipMemcpy(d_ranges, ranges.data(), sizeof(int32_t) * ranges.size(),
                                                hipMemcpyHostToDevice)
                                    : e7;
-  if (e4 != hipSuccess || e5 != hipSuccess || e6 != hipSuccess || e8 != hipSuccess ||
-      max_vals * (int64_t)sizeof(double) > 64 * 1024) {
+  // a range's LDS segment must fit next to the staging buffers (checked again at launch)
+  const bool too_big = max_vals * (int64_t)sizeof(double) > 96 * 1024;
+  if (e4 != hipSuccess || e5 != hipSuccess || e6 != hipSuccess || e8 != hipSuccess || too_big) {
     (void)hipFree(d_row_off); (void)hipFree(d_cols); (void)hipFree(d_rank);
     (void)hipFree(d_adj_off); (void)hipFree(d_adj); (void)hipFree(d_ranges);
-    return max_vals * (int64_t)sizeof(double) > 64 * 1024 ? TLFEA_ERR_UNSUPPORTED : TLFEA_ERR_HIP;
+    return too_big ? TLFEA_ERR_UNSUPPORTED : TLFEA_ERR_HIP;
   }
   // replace a previous pattern, if any
   (void)hipFree(m.d_row_off); (void)hipFree(m.d_cols); (void)hipFree(m.d_rank);
@@ -364,9 +370,25 @@ int build_pattern(Mesh& m) {
   m.n_ranges = (int)m.h_ranges.size() - 1;
   m.max_range_values = max_vals;
   m.max_range_rows = max_rows;
+  m.tune = tune;
   m.nnz = nnz;
   m.has_pattern = true;
   return TLFEA_OK;
+}
+
+static int env_int(const char* name, int fallback, int lo, int hi) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return fallback;
+  const long x = std::strtol(v, nullptr, 10);
+  return (x < lo || x > hi) ? fallback : (int)x;
+}
+
+GatherTuning gather_tuning() {
+  GatherTuning t;
+  t.waves = env_int("TLFEA_GATHER_WAVES", t.waves, 1, 4);
+  t.range_tasks = env_int("TLFEA_RANGE_TASKS", t.range_tasks, 1, 1 << 20);
+  t.range_values = env_int("TLFEA_RANGE_VALUES", t.range_values, 1, 12 * 1024);
+  return t;
 }
 
 int export_slot_map(const Mesh& m, int64_t e0, int64_t ne, int32_t* d_out, hipStream_t s) {

@@ -22,6 +22,25 @@
 
 namespace tlfea {
 
+constexpr int kStageThreads = 256;     // (element, point) indices per pass-1 workgroup
+constexpr int kMaxRangeNodes = 64;      // nodes per pass-2 workgroup
+
+// Bytes per (element, node) row of the slot map: padded so that a row is one
+// aligned vector load (T10: 10 ranks in 16 bytes, ANCF: 4 ranks in 4 bytes).
+constexpr int rank_stride(int npn) { return npn <= 4 ? 4 : 16; }
+
+// Pass-2 launch shape.  Node ranges are cut so that a range has at most
+// range_tasks tasks (lanes) and range_values LDS doubles (a single node may
+// exceed both); a workgroup of `waves` waves processes one range.
+struct GatherTuning {
+  int waves = 4;
+  int range_tasks = 768;
+  int range_values = 4096;
+};
+// defaults, overridden by TLFEA_GATHER_WAVES / TLFEA_RANGE_TASKS /
+// TLFEA_RANGE_VALUES when set (tuning sweeps)
+GatherTuning gather_tuning();
+
 // Per-mesh state.  All d_* members are device allocations owned by the mesh.
 struct Mesh {
   int device = 0;
@@ -55,6 +74,7 @@ struct Mesh {
   int n_ranges = 0;
   int64_t max_range_values = 0;   // largest LDS segment (CSR values + force rows), in doubles
   int64_t max_range_rows = 0;     // largest number of force rows of a range
+  GatherTuning tune;              // launch shape the ranges were cut for
   void* d_stage = nullptr;        // pass-1 records
   size_t stage_cap = 0;
   int staged = 0;                 // what the last pass 1 left: 0 none, 1 force records, 2 force + tangent
@@ -66,7 +86,7 @@ struct Mesh {
   int32_t* d_cols = nullptr;      // nnz
   int32_t* d_adj_off = nullptr;   // n_pnodes + 1, pattern-node adjacency
   int32_t* d_adj = nullptr;
-  uint8_t* d_rank = nullptr;      // n_elem * n_pn * n_pn: rank of node b in adj(node a)
+  uint8_t* d_rank = nullptr;      // n_elem * n_pn rows of rank_stride(n_pn) bytes: rank of node b in adj(node a)
   hipStream_t last_stream = nullptr;
 };
 
@@ -91,9 +111,6 @@ struct AsmArgs {
   uint32_t* flags;
 };
 
-constexpr int kMaxRangeNodes = 64;      // nodes per pass-2 workgroup
-constexpr int kRangeTasks = 256;        // target tasks (lanes) per pass-2 workgroup
-constexpr int kRangeValues = 4096;      // target LDS doubles per pass-2 workgroup
 
 // Pass-2 arguments of one mesh.
 struct GatherArgs {
@@ -120,7 +137,7 @@ struct BatchBody {
   const uint8_t* rank;
   const int32_t* inc_off;
   const int32_t* inc;
-  int64_t n_elem, dof_off, nnz_off, point_off;
+  int64_t n_elem, dof_off, nnz_off, point_off, block_off;
   int affine;
   double half_h;
   MatParams mp;
@@ -132,7 +149,7 @@ struct BatchArgs {
   const BatchBody* bodies;
   const BatchRange* ranges;
   int n_bodies;
-  int64_t n_points;
+  int64_t n_points, n_blocks;
   void* stage;
   const double* q;
   const double* qdot;
@@ -147,8 +164,8 @@ MatParams make_params(int material, const double* params, double eta, double lam
 // bytes of pass-1 records for a mesh / per record
 size_t stage_bytes(const Mesh& m, bool want_k);
 size_t stage_record_bytes(int precision);
-int launch_batch(int elem_type, int gl0, int precision, const BatchArgs& b, int n_ranges, size_t lds,
-                 hipStream_t s);
+int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tune, const BatchArgs& b,
+                 int n_ranges, size_t lds, hipStream_t s);
 
 // kernel launchers (assemble.hip)
 int launch_zero(double* p, int64_t n, hipStream_t s);

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(64) void k_vjp(AsmArgs a, const double* w, double* 
       double* out = pass == 0 ? gq : gqd;
       if (!out) continue;
       double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-      sfor<0, NQ>([&](auto qc) {
+      sfor<0, NQ>([&](auto qc) __attribute__((always_inline)) {
         constexpr int q = decltype(qc)::value;
         const double* s = lds + (el * NQ + q) * 24 + 12 * pass;
         const double d0 = Rule::dN_rt(q, al, 0), d1 = Rule::dN_rt(q, al, 1), d2 = Rule::dN_rt(q, al, 2);

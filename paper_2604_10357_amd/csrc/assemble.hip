@@ -357,8 +357,10 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   constexpr int PD = UNROLL ? (sizeof(R) == 4 ? NQ : 3) : PB;  // points whose pieces are in flight
   constexpr int NB = WANT_K ? NEN : 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-  R* wbuf = reinterpret_cast<R*>(smem) + wave * NI * REC;
-  double* lds = reinterpret_cast<double*>(smem + nwave * wave_buf_bytes<Rule, R, WANT_K>());
+  // LDS: incidence -> node table, wave record buffers, CSR segment + forces
+  uint8_t* incn = smem;
+  R* wbuf = reinterpret_cast<R*>(smem + g.inc_cap) + wave * NI * REC;
+  double* lds = reinterpret_cast<double*>(smem + g.inc_cap + nwave * wave_buf_bytes<Rule, R, WANT_K>());
   const int nn = I1 - I0;
   const int64_t row0 = (int64_t)RPN * I0, row1 = (int64_t)RPN * I1;
   const int64_t seg0 = WANT_K ? g.row_off[row0] : 0, seg1 = WANT_K ? g.row_off[row1] : 0;
@@ -373,6 +375,10 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   // segment-relative offsets of the range's CSR rows
   if constexpr (WANT_K)
     for (int rr = tid; rr < nrow; rr += blockDim.x) rowo[rr] = (int32_t)(g.row_off[row0 + rr] - seg0);
+  __syncthreads();
+  // range-local node of every incidence (nodes < kMaxRangeNodes fit a byte)
+  for (int n = tid; n < nn; n += blockDim.x)
+    for (int j = pre[n] / TPI; j < pre[n + 1] / TPI; ++j) incn[j] = (uint8_t)n;
   __syncthreads();
   const int ntask = pre[nn];
   const R* stage = (const R*)g.stage;
@@ -419,11 +425,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
     });
     const int32_t packed = ime;
     if (t0 + (int)blockDim.x < ntask) fetch_inc(t0 + blockDim.x, icp, ime);
-    int n = 0, hi = nn - 1;  // last node whose first task is <= t
-    while (n < hi) {
-      const int mid = (n + hi + 1) >> 1;
-      if (pre[mid] <= t) n = mid; else hi = mid - 1;
-    }
+    const int n = incn[t / TPI];
     const int r = t % TPI, ca = r / 9, i = (r / 3) % 3, k = r % 3;  // pre[] holds multiples of TPI
     const int64_t e = packed >> 4;
     const int a = packed & 15;
@@ -519,7 +521,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
 }
 
 template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM>
-__global__ __launch_bounds__(256) void k_gather(GatherArgs g) {
+__global__ __launch_bounds__(512) void k_gather(GatherArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t pre[kMaxRangeNodes + 1];
   __shared__ int32_t rowo[kMaxRangeNodes * 3 * Rule::MC];
@@ -528,7 +530,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs g) {
 }
 
 template <class Rule, typename R>
-__global__ __launch_bounds__(256) void k_gather_batch(BatchArgs b) {
+__global__ __launch_bounds__(512) void k_gather_batch(BatchArgs b) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t pre[kMaxRangeNodes + 1];
   __shared__ int32_t rowo[kMaxRangeNodes * 3 * Rule::MC];
@@ -546,6 +548,7 @@ __global__ __launch_bounds__(256) void k_gather_batch(BatchArgs b) {
   g.stage = (const R*)b.stage + B.point_off * kRecK;
   g.f = b.f + B.dof_off;
   g.vals = b.vals + B.nnz_off;
+  g.inc_cap = b.inc_cap;
   gather_range<Rule, R, true, true, false>(g, br.I0, br.I1, smem, pre, rowo);
 }
 
@@ -600,7 +603,8 @@ int launch_nodes_rule(const Mesh& m, double* f, double* vals, bool accum, hipStr
   g.stage = stage;
   g.f = f;
   g.vals = vals;
-  const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows) +
+  g.inc_cap = (int)((m.max_range_inc + 15) / 16 * 16);
+  const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows) + g.inc_cap +
                      (size_t)m.tune.waves * (want_k ? wave_buf_bytes<Rule, R, true>() : wave_buf_bytes<Rule, R, false>());
   const dim3 grid((unsigned)m.n_ranges), blk(64 * m.tune.waves);
 #define TLFEA_GATHER(F, K, A)                                                \
@@ -639,7 +643,7 @@ int launch_batch_rule(const GatherTuning& tu, const BatchArgs& b, int n_ranges, 
   if (b.n_blocks > 0)
     hipLaunchKernelGGL((k_stage_batch<Rule, R>), dim3((unsigned)b.n_blocks), dim3(kStageThreads), 0, s, b);
   TLFEA_HIP_CHECK(hipGetLastError());
-  const size_t lds_all = lds + (size_t)tu.waves * wave_buf_bytes<Rule, R, true>();
+  const size_t lds_all = lds + b.inc_cap + (size_t)tu.waves * wave_buf_bytes<Rule, R, true>();
   if (int rc = allow_lds(k_gather_batch<Rule, R>, lds_all)) return rc;
   hipLaunchKernelGGL((k_gather_batch<Rule, R>), dim3(n_ranges), dim3(64 * tu.waves), lds_all, s, b);
   TLFEA_HIP_CHECK(hipGetLastError());

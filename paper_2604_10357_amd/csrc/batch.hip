@@ -28,6 +28,7 @@ struct tlfea_batch_s {
   int n_ranges = 0;
   int64_t n_points = 0, n_blocks = 0;
   size_t lds = 0;
+  int inc_cap = 0;
   void* d_stage = nullptr;
   uint32_t* d_flags = nullptr;
   // graph cache, keyed by the argument pointers and the stream
@@ -94,6 +95,7 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
     b->n_blocks += (m.n_elem * m.n_qp + tlfea::kStageThreads - 1) / tlfea::kStageThreads;
     for (int r = 0; r < m.n_ranges; ++r) ranges.push_back(BatchRange{i, m.h_ranges[r], m.h_ranges[r + 1]});
     max_vals = std::max(max_vals, m.max_range_values);
+    b->inc_cap = std::max(b->inc_cap, (int)((m.max_range_inc + 15) / 16 * 16));
     b->meshes.push_back(meshes[i]);
   }
   if (ranges.size() > (size_t)INT32_MAX || b->n_blocks > INT32_MAX) { delete b; return TLFEA_ERR_TOO_LARGE; }
@@ -149,6 +151,7 @@ TLFEA_API int tlfea_batch_assemble(tlfea_batch_t b, const double* d_q, const dou
   a.n_bodies = (int)b->meshes.size();
   a.n_points = b->n_points;
   a.n_blocks = b->n_blocks;
+  a.inc_cap = b->inc_cap;
   a.stage = b->d_stage;
   a.q = d_q;
   a.qdot = d_qdot;

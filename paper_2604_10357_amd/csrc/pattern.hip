@@ -317,9 +317,9 @@ int build_pattern(Mesh& m) {
   // greedy partition of the nodes into ranges of bounded tasks and LDS values
   const GatherTuning tune = gather_tuning();
   std::vector<int32_t> ranges{0};
-  int64_t max_vals = 0, max_rows = 0;
+  int64_t max_vals = 0, max_rows = 0, max_inc = 0;
   {
-    int64_t tasks = 0, vals = 0, rows = 0, nodes = 0;
+    int64_t tasks = 0, vals = 0, rows = 0, nodes = 0, incs = 0;
     for (int64_t I = 0; I < nn; ++I) {
       const int64_t tI = 9LL * mc * (h_inc_off[I + 1] - h_inc_off[I]);
       const int64_t vI = 9LL * mc * mc * (h_adj_off[I + 1] - h_adj_off[I]) + 3LL * mc;
@@ -327,8 +327,10 @@ int build_pattern(Mesh& m) {
         ranges.push_back((int32_t)I);
         max_vals = std::max(max_vals, vals);
         max_rows = std::max(max_rows, rows);
-        tasks = vals = rows = nodes = 0;
+        max_inc = std::max(max_inc, incs);
+        tasks = vals = rows = nodes = incs = 0;
       }
+      incs += h_inc_off[I + 1] - h_inc_off[I];
       tasks += tI;
       vals += vI;
       rows += 3LL * mc;
@@ -338,6 +340,7 @@ int build_pattern(Mesh& m) {
       ranges.push_back((int32_t)nn);
       max_vals = std::max(max_vals, vals);
       max_rows = std::max(max_rows, rows);
+      max_inc = std::max(max_inc, incs);
     }
   }
   int32_t* d_ranges = nullptr;
@@ -370,6 +373,7 @@ int build_pattern(Mesh& m) {
   m.n_ranges = (int)m.h_ranges.size() - 1;
   m.max_range_values = max_vals;
   m.max_range_rows = max_rows;
+  m.max_range_inc = max_inc;
   m.tune = tune;
   m.nnz = nnz;
   m.has_pattern = true;
@@ -385,7 +389,7 @@ static int env_int(const char* name, int fallback, int lo, int hi) {
 
 GatherTuning gather_tuning() {
   GatherTuning t;
-  t.waves = env_int("TLFEA_GATHER_WAVES", t.waves, 1, 4);
+  t.waves = env_int("TLFEA_GATHER_WAVES", t.waves, 1, 8);
   t.range_tasks = env_int("TLFEA_RANGE_TASKS", t.range_tasks, 1, 1 << 20);
   t.range_values = env_int("TLFEA_RANGE_VALUES", t.range_values, 1, 12 * 1024);
   return t;

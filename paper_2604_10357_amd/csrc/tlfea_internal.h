@@ -74,6 +74,7 @@ struct Mesh {
   int n_ranges = 0;
   int64_t max_range_values = 0;   // largest LDS segment (CSR values + force rows), in doubles
   int64_t max_range_rows = 0;     // largest number of force rows of a range
+  int64_t max_range_inc = 0;      // largest number of incidences of a range
   GatherTuning tune;              // launch shape the ranges were cut for
   void* d_stage = nullptr;        // pass-1 records
   size_t stage_cap = 0;
@@ -124,6 +125,7 @@ struct GatherArgs {
   const void* stage;
   double* f;
   double* vals;
+  int inc_cap;  // LDS bytes for the range's incidence -> node table (multiple of 16)
 };
 
 // Batched launch: one descriptor per body; pass 1 runs over the concatenated
@@ -157,6 +159,7 @@ struct BatchArgs {
   double* f;
   double* vals;
   uint32_t* flags;
+  int inc_cap;  // LDS bytes for a range's incidence -> node table (multiple of 16)
 };
 
 MatParams make_params(int material, const double* params, double eta, double lam_v);

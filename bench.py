@@ -1,16 +1,20 @@
 """Benchmark: fused internal force + tangent assembly on one MI355X.
 
-Default workload: the large T10 beam (200 x 20 x 20 Kuhn cells = 480,000
-quadratic tetrahedra, 2,022,243 DOF, 169,094,889 CSR values), Mooney-Rivlin +
-Kelvin-Voigt, mixed precision, one `tlfea_assemble` call per step (clear f and
-the CSR values, then f_int and h * df/dq + df/dqdot with h = 1e-3).  Inputs are
-resident in HBM before the timed region.  The FP64 form is timed on the same
-mesh for comparison.
+Default workload (`--workload t10_beam`): the large T10 beam (200 x 20 x 20
+Kuhn cells = 480,000 quadratic tetrahedra, 2,022,243 DOF, 169,094,889 CSR
+values), Mooney-Rivlin + Kelvin-Voigt, mixed precision, one `tlfea_assemble`
+call per step (f_int and h * df/dq + df/dqdot with h = 1e-3, outputs
+overwritten).  Inputs are resident in HBM before the timed region.  The FP64
+form is timed on the same mesh for comparison.  Other workloads: `t10_box`
+(80 x 8 x 8 cells), `ancf_plate` (256 x 256 ANCF3443 shell, SVK, 3x3x2 rule)
+and `batched` (512 T10 cubes in one graph-captured launch pair, against the
+per-body loop).
 
 Prints one JSON line: metric / value (elements per second, whole call),
-roofline of the dominant kernel (algorithmic bytes / its event-timed duration
-against 8 TB/s), FP64 comparison, errors against the CPU oracle and the CPU
-oracle's own throughput on a bounded sample of the same mesh.
+roofline of the hot path (algorithmic bytes / its event-timed duration against
+8 TB/s, and the counter-measured HBM traffic when it is on record for these
+kernels), FP64 comparison, errors against the CPU oracle and the CPU oracle's
+own throughput on a bounded sample of the same mesh.
 """
 from __future__ import annotations
 
@@ -29,13 +33,25 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_t10_beam_200x20x20_mixed.json")
 
 
-def algorithmic_bytes(n_el, n_dof, nnz, n_pn=10, geo_bytes=80):
+def algorithmic_bytes(n_el, n_dof, nnz, n_pn=10, geo_bytes=80, extra_per_elem=0, want_k=True):
     """Bytes one fused f + K call must move with this library's data layout:
     K values written once (8 nnz), f written once (8 n_dof), q, qdot and X read
     once (24 n_dof), CSR row offsets (4 n_dof), connectivity (4 n_pn per
-    element), reference geometry (80 B per affine element: J0^-1 and det J0) and
-    the one-byte node-rank slot map (n_pn^2 per element)."""
-    return 8 * nnz + 8 * n_dof + 24 * n_dof + 4 * (n_dof + 1) + n_el * (4 * n_pn + geo_bytes + n_pn * n_pn)
+    element), reference geometry (80 B per affine element: J0^-1 and det J0;
+    per point otherwise), the one-byte node-rank slot map (n_pn^2 per element)
+    and per-element scales (ANCF: 16 B)."""
+    b = 8 * n_dof + 24 * n_dof + n_el * (4 * n_pn + geo_bytes + extra_per_elem)
+    if want_k:
+        b += 8 * nnz + 4 * (n_dof + 1) + n_el * n_pn * n_pn
+    return b
+
+
+def mesh_bytes(wl, nnz, affine=True):
+    m = wl.mesh
+    if m.elem_type == 1:  # T10
+        return algorithmic_bytes(m.n_elem, m.n_dof, nnz, 10, 80 if affine else 80 * 5)
+    nq = int(np.prod(m.gl))
+    return algorithmic_bytes(m.n_elem, m.n_dof, nnz, 4, 80 if affine else 80 * nq, 16)
 
 
 def measured_traffic(precision):
@@ -72,36 +88,39 @@ def time_calls(fn, steps, torch):
 
 def cpu_baseline(wl, f_gpu, vals_gpu, ro, cols, h, budget_s=12.0):
     """Time the FP64 CPU oracle on a bounded sample (the first elements of the
-    mesh, i.e. whole x-slabs) and compare the GPU rows of the nodes whose every
-    incident element lies in the sample."""
+    mesh) and compare the GPU rows of the nodes whose every incident element
+    lies in the sample."""
+    import dataclasses
+
     import oracle
-    from paper_2604_10357_amd import workloads as W
 
     oracle.build(force=False)
     omat = oracle.material_of(wl.material)
-    # calibrate on a small slab, then size the sample to the budget
-    n_cal = 2400
-    sub = W.Mesh(W.T10, wl.mesh.X, wl.mesh.conn[:n_cal].copy())
-    om = oracle.Mesh.of(sub)
-    pat = oracle.csr_pattern(om)
+    n_el = wl.mesh.n_elem
+    mc = 1 if wl.mesh.elem_type == 1 else 4
+
+    def sample(n):
+        sub = dataclasses.replace(wl.mesh, conn=wl.mesh.conn[:n].copy())
+        om = oracle.Mesh.of(sub)
+        return sub, om, oracle.csr_pattern(om)
+
+    n_cal = min(n_el, 2400)
+    sub, om, pat = sample(n_cal)
     t0 = time.perf_counter()
     oracle.assemble(om, omat, wl.q, wl.qdot, h, 1.0, pattern=pat)
     per_el = (time.perf_counter() - t0) / n_cal
-    n = int(min(wl.mesh.n_elem, max(n_cal, budget_s / per_el)))
-    n = max(2400, (n // 2400) * 2400)  # whole slabs of 20 x 20 cells
-    sub = W.Mesh(W.T10, wl.mesh.X, wl.mesh.conn[:n].copy())
-    om = oracle.Mesh.of(sub)
-    pat = oracle.csr_pattern(om)
+    n = int(min(n_el, max(n_cal, budget_s / per_el)))
+    sub, om, pat = sample(n)
     t0 = time.perf_counter()
     f_ref, v_ref = oracle.assemble(om, omat, wl.q, wl.qdot, h, 1.0, pattern=pat)
     dt = time.perf_counter() - t0
-    # nodes all of whose elements are in the sample
-    inc_all = np.zeros(wl.mesh.n_coef, dtype=np.int64)
-    np.add.at(inc_all, wl.mesh.conn.ravel(), 1)
-    inc_sub = np.zeros(wl.mesh.n_coef, dtype=np.int64)
-    np.add.at(inc_sub, sub.conn.ravel(), 1)
+    # pattern nodes all of whose elements are in the sample
+    n_pnodes = int(wl.mesh.conn.max()) + 1
+    inc_all = np.bincount(wl.mesh.conn.ravel(), minlength=n_pnodes)
+    inc_sub = np.bincount(sub.conn.ravel(), minlength=n_pnodes)
     inner = np.nonzero((inc_sub == inc_all) & (inc_sub > 0))[0]
-    rows = (3 * inner[:, None] + np.arange(3)[None, :]).ravel()
+    coefs = (mc * inner[:, None] + np.arange(mc)[None, :]).ravel()
+    rows = (3 * coefs[:, None] + np.arange(3)[None, :]).ravel()
     errs = {}
     ef = np.abs(f_gpu[rows] - f_ref[rows]).max() / np.abs(f_ref[rows]).max()
     ro_s, cols_s = pat
@@ -115,32 +134,32 @@ def cpu_baseline(wl, f_gpu, vals_gpu, ro, cols, h, budget_s=12.0):
     errs["f"] = float(ef)
     errs["K"] = float(kd / kmax)
     base = {"value": n / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} of {wl.mesh.n_elem} elements (whole x-slabs), fused f + K, FP64 C oracle, "
-                      f"{dt:.1f} s single-threaded"}
+            "sample": f"first {n} of {n_el} elements, fused f + K, FP64 C oracle, {dt:.1f} s single-threaded"}
     return base, errs, len(rows)
 
 
-def main(argv=None):
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    args = ap.parse_args(argv)
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
-        return 2
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (GB/s, read + write bytes) as the achievable HBM rate."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    ms = time_calls(lambda: b.copy_(a), reps, torch)
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
-    import torch
 
-    from paper_2604_10357_amd import workloads as W
+WORKLOADS = {
+    "t10_beam": ("config5", "t10_beam_200x20x20_mr_kv"),
+    "t10_box": ("config2", "t10_box_80x8x8_mr_kv"),
+    "ancf_plate": ("config3", "ancf3443_plate_256x256_svk"),
+}
+
+
+def bench_mesh(args, torch, wl, wname):
     from paper_2604_10357_amd.api import TLMesh
 
-    torch.cuda.set_device(0)
     t_setup = time.perf_counter()
-    wl = W.config5()
     n_el, n_dof = wl.mesh.n_elem, wl.mesh.n_dof
     mesh = TLMesh(wl.mesh, wl.material, args.precision)
     nnz = mesh.build_pattern()
@@ -150,7 +169,7 @@ def main(argv=None):
     vals = torch.empty(nnz, dtype=torch.float64, device="cuda")
     h = 1e-3
     torch.cuda.synchronize()
-    print(f"[bench] setup {time.perf_counter() - t_setup:.1f} s: {n_el} elements, {n_dof} dof, nnz {nnz}",
+    print(f"[bench] {wname} setup {time.perf_counter() - t_setup:.1f} s: {n_el} elements, {n_dof} dof, nnz {nnz}",
           file=sys.stderr, flush=True)
 
     def step():
@@ -176,9 +195,13 @@ def main(argv=None):
     # the hot path is the pair of kernels k_stage_tile (pass 1) + k_gather
     # (pass 2), timed together with events on the stream they run on; its
     # algorithmic bytes are set against the time of the whole call
-    B = algorithmic_bytes(n_el, n_dof, nnz)
+    B = mesh_bytes(wl, nnz)
     achieved = B / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.precision)
+    traffic = measured_traffic(args.precision) if wname == "t10_beam" else None
+    kname = "T10" if wl.mesh.elem_type == 1 else "ANCF3443"
+    mat = "mooney_rivlin" if wl.material.kind == 2 else "svk"
+    if wl.material.kv_eta or wl.material.kv_lambda:
+        mat += "+kelvin_voigt"
     out = {
         "metric": "f_int+K assembly elements/s and HBM GB/s; mixed vs FP64 at stated error",
         "value": n_el / (ms * 1e-3),
@@ -192,11 +215,11 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "t10_beam_200x20x20_mr_kv", "elements": n_el, "dof": n_dof, "nnz": nnz,
-                   "precision": args.precision, "material": "mooney_rivlin+kelvin_voigt", "h": h},
+        "config": {"workload": WORKLOADS[wname][1], "elements": n_el, "dof": n_dof, "nnz": nnz,
+                   "precision": args.precision, "material": mat, "h": h},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_stage_tile + k_gather (T10, f + K)", "kernel_ms": ms,
+                     "kernel": f"k_stage_tile + k_gather ({kname}, f + K)", "kernel_ms": ms,
                      "pass1_stage_ms": ms1, "pass2_gather_ms": ms2, "algorithmic_bytes": B},
     }
     ro, cols = mesh.csr_pattern(on_device=False)
@@ -220,11 +243,96 @@ def main(argv=None):
             "f": float(np.abs(f_h - f64).max() / np.abs(f64).max()),
             "K": float(np.abs(v_h - v64).max() / np.abs(v64).max())}
         print(f"[bench] fp64: {ms64:.4f} ms per call", file=sys.stderr, flush=True)
+    if wname == "t10_beam":
+        # context: the backward product on the same mesh, and a plain device copy
+        w = torch.from_numpy(wl.w).cuda() if wl.w is not None else torch.ones_like(q)
+        mesh.vjp(q, qd, w)
+        out["vjp_ms"] = time_calls(lambda: mesh.vjp(q, qd, w), max(3, args.steps // 4), torch)
+        out["copy_GBs"] = copy_bandwidth(torch)
     if not args.no_cpu_baseline:
         base, errs, nrows = cpu_baseline(wl, f_h, v_h, ro, cols, h)
         out["cpu_baseline"] = base
-        out["error_vs_oracle"] = dict(errs, rows=nrows, precision=args.precision, gate=1e-5 if args.precision == "mixed" else 1e-12)
+        out["error_vs_oracle"] = dict(errs, rows=nrows, precision=args.precision,
+                                      gate=1e-5 if args.precision == "mixed" else 1e-12)
     mesh.close()
+    return out
+
+
+def bench_batched(args, torch):
+    """Config-4 style batch: 512 T10 cubes, one graph-captured launch pair vs a
+    loop of per-body calls."""
+    from paper_2604_10357_amd import workloads as W
+    from paper_2604_10357_amd.api import TLBatch, TLMesh
+
+    wls = W.config4()
+    meshes = []
+    for wl in wls:
+        m = TLMesh(wl.mesh, wl.material, args.precision)
+        m.build_pattern()
+        meshes.append(m)
+    b = TLBatch(meshes)
+    q = torch.from_numpy(np.concatenate([wl.q for wl in wls])).cuda()
+    qd = torch.from_numpy(np.concatenate([wl.qdot for wl in wls])).cuda()
+    hs = torch.full((len(wls),), 1e-3, dtype=torch.float64, device="cuda")
+    nd, nz = b.dof_off[-1], b.nnz_off[-1]
+    f = torch.empty(nd, dtype=torch.float64, device="cuda")
+    vals = torch.empty(nz, dtype=torch.float64, device="cuda")
+    n_el = sum(wl.mesh.n_elem for wl in wls)
+    B = sum(mesh_bytes(wl, m.nnz) for wl, m in zip(wls, meshes))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for _ in range(args.warmup):
+            b.assemble(q, qd, hs, f, vals)
+        ms = time_calls(lambda: b.assemble(q, qd, hs, f, vals), args.steps, torch)
+        for _ in range(args.warmup):
+            b.assemble(q, qd, hs, f, vals, loop=True)
+        ms_loop = time_calls(lambda: b.assemble(q, qd, hs, f, vals, loop=True), args.steps, torch)
+    s.synchronize()
+    achieved = B / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "f_int+K assembly elements/s and HBM GB/s; mixed vs FP64 at stated error",
+        "value": n_el / (ms * 1e-3), "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "t10_cubes_x512_batched", "bodies": len(wls), "elements": n_el, "dof": int(nd),
+                   "nnz": int(nz), "precision": args.precision},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stage_batch + k_gather_batch (one graph)", "kernel_ms": ms,
+                     "algorithmic_bytes": B},
+        "per_body_loop": {"ms_per_step": ms_loop, "value": n_el / (ms_loop * 1e-3),
+                          "speedup_batched_over_loop": ms_loop / ms},
+    }
+    b.close()
+    for m in meshes:
+        m.close()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--workload", default="t10_beam", choices=list(WORKLOADS) + ["batched"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2604_10357_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    if args.workload == "batched":
+        out = bench_batched(args, torch)
+    else:
+        wl = getattr(W, WORKLOADS[args.workload][0])()
+        out = bench_mesh(args, torch, wl, args.workload)
     print(json.dumps(out), flush=True)
     return 0
 

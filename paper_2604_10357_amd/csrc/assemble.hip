@@ -589,9 +589,8 @@ int launch_points_rule(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t
 }
 
 template <class Rule, typename R>
-int launch_nodes_rule(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s) {
+int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals, bool accum, hipStream_t s) {
   const bool want_f = f != nullptr, want_k = vals != nullptr;
-  R* stage = (R*)m.d_stage;
   GatherArgs g{};
   g.ranges = m.d_ranges;
   g.inc_off = m.d_inc_off;
@@ -633,9 +632,9 @@ int launch_points_prec(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t
 
 template <typename R>
 int launch_nodes_prec(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s) {
-  if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, R>(m, f, vals, accum, s);
-  if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, R>(m, f, vals, accum, s);
-  return launch_nodes_rule<RuleAncf<4, 4, 3>, R>(m, f, vals, accum, s);
+  if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, R>(m, m.d_stage, f, vals, accum, s);
+  if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, R>(m, m.d_stage, f, vals, accum, s);
+  return launch_nodes_rule<RuleAncf<4, 4, 3>, R>(m, m.d_stage, f, vals, accum, s);
 }
 
 template <class Rule, typename R>
@@ -688,6 +687,13 @@ int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t
   }
   if (m.precision == TLFEA_MIXED) return launch_nodes_prec<float>(m, f, vals, accum, s);
   return launch_nodes_prec<double>(m, f, vals, accum, s);
+}
+
+int launch_force_gather_f64(const Mesh& m, const double* records, double* out, hipStream_t s) {
+  if (m.n_ranges == 0) return launch_zero(out, m.n_dof, s);
+  if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, double>(m, records, out, nullptr, false, s);
+  if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, double>(m, records, out, nullptr, false, s);
+  return launch_nodes_rule<RuleAncf<4, 4, 3>, double>(m, records, out, nullptr, false, s);
 }
 
 int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tu, const BatchArgs& b,

@@ -239,17 +239,46 @@ __device__ __forceinline__ unsigned point_update(const MatParams& mp, const doub
   return flags;
 }
 
-// Entry A_iJkL of the factored tangent (scaled by dV).
+// Z_kL = sum_iJ Wc_iJ A_iJkL (the tangent applied to a cotangent gradient Wc
+// from the left), term by term from the factored form:
+//   d_ik M_JL      -> (Wc M)_kL          N_ik d_JL  -> (N^T Wc)_kL
+//   F_iJ W_kL      -> (Wc:F) W_kL        F_iL Y_kJ  -> (Y Wc^T F)_kL
+//   U_iJ G_kL      -> (Wc:U) G_kL        G_iJ V_kL  -> (Wc:G) V_kL
+//   c G_iL G_kJ    -> c (G Wc^T G)_kL
 template <typename R>
-__device__ __forceinline__ R tangent_entry(const PointOut<R>& o, int i, int J, int k, int L) {
-  const R* F = o.F;
-  R a = F[3 * i + J] * o.W[3 * k + L] + F[3 * i + L] * o.Y[3 * k + J];
-  if (i == k) a += o.M[3 * J + L];
-  if (J == L) a += o.N[3 * i + k];
-  if (o.mr)
-    a += o.U[3 * i + J] * o.G[3 * k + L] + o.G[3 * i + J] * o.V[3 * k + L] +
-         o.cgx * o.G[3 * i + L] * o.G[3 * k + J];
-  return a;
+__device__ __forceinline__ void cotangent_contract(const PointOut<R>& o, const R* Wc, R* Z) {
+  R wf = R(0), wu = R(0), wg = R(0);
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    wf += Wc[t] * o.F[t];
+    if (o.mr) {
+      wu += Wc[t] * o.U[t];
+      wg += Wc[t] * o.G[t];
+    }
+  }
+  R T[9], S[9];  // Wc^T F and Wc^T G
+#pragma unroll
+  for (int J = 0; J < 3; ++J)
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+      T[3 * J + L] = Wc[J] * o.F[L] + Wc[3 + J] * o.F[3 + L] + Wc[6 + J] * o.F[6 + L];
+      S[3 * J + L] = o.mr ? Wc[J] * o.G[L] + Wc[3 + J] * o.G[3 + L] + Wc[6 + J] * o.G[6 + L] : R(0);
+    }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+      R z = wf * o.W[3 * k + L];
+#pragma unroll
+      for (int J = 0; J < 3; ++J)
+        z += Wc[3 * k + J] * o.M[3 * J + L] + o.N[3 * J + k] * Wc[3 * J + L] + o.Y[3 * k + J] * T[3 * J + L];
+      if (o.mr) {
+        z += wu * o.G[3 * k + L] + wg * o.V[3 * k + L];
+#pragma unroll
+        for (int J = 0; J < 3; ++J) z += o.cgx * o.G[3 * k + J] * S[3 * J + L];
+      }
+      Z[3 * k + L] = z;
+    }
 }
 
 // The same tangent and stress in parent coordinates, with dV folded in:

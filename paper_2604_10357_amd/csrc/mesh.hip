@@ -426,6 +426,19 @@ TLFEA_API int tlfea_get_slot_map(tlfea_mesh_t mesh, int64_t elem_begin, int64_t 
   return TLFEA_OK;
 }
 
+namespace tlfea {
+int ensure_stage(Mesh& m, size_t need) {
+  if (m.stage_cap >= need) return TLFEA_OK;
+  (void)hipFree(m.d_stage);  // synchronises with work that may still read it
+  m.d_stage = nullptr;
+  m.stage_cap = 0;
+  m.staged = 0;
+  TLFEA_HIP_CHECK(hipMalloc(&m.d_stage, need));
+  m.stage_cap = need;
+  return TLFEA_OK;
+}
+}  // namespace tlfea
+
 // pass 1 of an assembly: per-point records in the mesh's work buffer
 static int run_points(tlfea_mesh_t mesh, const double* q, const double* qdot, double alpha, double beta, bool want_k,
                       void* stream) {
@@ -435,15 +448,7 @@ static int run_points(tlfea_mesh_t mesh, const double* q, const double* qdot, do
   Mesh& m = mesh->m;
   auto s = (hipStream_t)stream;
   m.last_stream = s;
-  const size_t need = tlfea::stage_bytes(m, want_k);
-  if (m.stage_cap < need) {
-    (void)hipFree(m.d_stage);  // synchronises with work that may still read it
-    m.d_stage = nullptr;
-    m.stage_cap = 0;
-    m.staged = 0;
-    TLFEA_HIP_CHECK(hipMalloc(&m.d_stage, need));
-    m.stage_cap = need;
-  }
+  if ((rc = tlfea::ensure_stage(m, tlfea::stage_bytes(m, want_k)))) return rc;
   tlfea::AsmArgs a = tlfea::make_args(m, q, qdot, nullptr, nullptr, alpha, beta);
   rc = tlfea::launch_points(m, a, want_k, s);
   m.staged = rc ? 0 : (want_k ? 2 : 1);
@@ -521,6 +526,7 @@ TLFEA_API int tlfea_internal_force_vjp(tlfea_mesh_t mesh, const double* d_q, con
   int rc = tlfea::check_call(mesh, d_q, false);
   if (rc) return rc;
   if (!d_w || (!d_gq && !d_gqdot && !d_gparam)) return TLFEA_ERR_INVALID;
+  if (!mesh->m.has_pattern) return TLFEA_ERR_NO_PATTERN;
   mesh->m.last_stream = (hipStream_t)stream;
   return tlfea::launch_vjp(mesh->m, d_q, d_qdot, d_w, d_gq, d_gqdot, d_gparam, (hipStream_t)stream);
 }

@@ -183,8 +183,14 @@ int export_slot_map(const Mesh& m, int64_t e0, int64_t ne, int32_t* d_out, hipSt
 // geometry precompute (mesh.hip)
 int precompute_geometry(Mesh& m);
 
+// work buffer of at least `bytes` (mesh.hip); reallocation synchronises
+int ensure_stage(Mesh& m, size_t bytes);
+// pass 2 over float64 force-type records (Phat_ik at 4 i + k, 12 per point)
+// at `records`, written to `out` (n_dof); used by the VJP (assemble.hip)
+int launch_force_gather_f64(const Mesh& m, const double* records, double* out, hipStream_t s);
+
 // VJP (vjp.hip)
-int launch_vjp(const Mesh& m, const double* q, const double* qdot, const double* w, double* gq,
+int launch_vjp(Mesh& m, const double* q, const double* qdot, const double* w, double* gq,
                double* gqdot, double* gparam, hipStream_t s);
 
 AsmArgs make_args(const Mesh& m, const double* q, const double* qdot, double* f, double* vals,

@@ -1,8 +1,8 @@
 // vjp.hip -- reverse-mode products of the internal force for autograd.
 //
-// For a cotangent w the kernel returns, without forming K:
+// For a cotangent w the library returns, without forming K:
 //   gq     = (df/dq)^T w     : per point Z_kL = sum_iJ W_iJ dP_iJ/dF_kL with
-//                              W = sum_a w_a (x) g_a, then gq_b += dV Z g_b
+//                              W = sum_a w_a (x) g_a, then gq_b = sum dV Z g_b
 //   gqdot  = (df/dqdot)^T w  : the same with dP/dFdot
 //   gparam = d(w . f)/dtheta : P is linear in every material constant, so the
 //                              partial is dV W : P(theta = e_i), reduced over
@@ -11,53 +11,50 @@
 // f itself follows Sec. 4.3 (Eqs. F_assembly, fint_local) of the paper; the
 // VJP is the transpose of the Sec. 4.4.2 tangent (Eq. tangent_block) applied
 // element by element.  Runs in float64.
+//
+// The per-node sums have exactly the form of f_int with the stress replaced by
+// Z: pass 1 (k_vjp_stage, one lane per element x point) stores
+// Zhat = dV Z J0^-T as a force-type record, and pass 2 is the force gather of
+// the assembly (per node range, LDS sums, plain stores; no global atomics).
 #include "kernel_common.h"
 
 namespace tlfea {
 namespace {
 
-template <class Rule, int TE>
-__global__ __launch_bounds__(64) void k_vjp(AsmArgs a, const double* w, double* gq, double* gqd, double* gacc) {
-  constexpr int NEN = Rule::NEN, NQ = Rule::NQ;
-  __shared__ double lds[TE * NQ * 24];
-  __shared__ double red[5];
-  const int lane = threadIdx.x;
-  const int tile = remap_tile(blockIdx.x, gridDim.x);
-  const int64_t e0 = (int64_t)tile * TE;
-  if (lane < 5) red[lane] = 0.0;
-  __syncthreads();
-  for (int p = lane; p < TE * NQ; p += 64) {
-    const int el = p / NQ, q = p % NQ;
-    const int64_t ge = e0 + el;
-    if (ge >= a.n_elem) continue;
+constexpr int kVjpThreads = 256;
+constexpr int kZRec = 12;  // force-type record: Zhat_km at 4 k + m
+
+template <class Rule>
+__global__ __launch_bounds__(kVjpThreads) void k_vjp_stage(AsmArgs a, const double* w, double* zq, double* zqd,
+                                                          double* gacc) {
+  constexpr int NQ = Rule::NQ;
+  __shared__ double red[kVjpThreads / 64][5];
+  const int64_t p = (int64_t)blockIdx.x * kVjpThreads + threadIdx.x;
+  double part[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (p < a.n_elem * NQ) {
+    const int64_t ge = p / NQ;
+    const int q = (int)(p % NQ);
     double Hd[9], Fd[9], Jinv[9], det, sc[4], Wg[9];
     load_kinematics<Rule>(a, ge, q, Hd, Fd, Jinv, det);
     element_scales<Rule>(a, ge, sc);
     field_gradient<Rule>(a, ge, q, sc, w, nullptr, Jinv, Wg);
     const double dV = det * Rule::w_rt(q);
-    double* s = lds + p * 24;
     for (int pass = 0; pass < 2; ++pass) {
-      if ((pass == 0 && !gq) || (pass == 1 && !gqd)) continue;
+      double* out = pass == 0 ? zq : zqd;
+      if (!out) continue;
       PointOut<double> o;
       (void)point_update<double, true>(a.mp, Hd, Fd, dV, pass == 0 ? 1.0 : 0.0, pass == 0 ? 0.0 : 1.0, o);
       double Z[9];
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int L = 0; L < 3; ++L) {
-          double z = 0.0;
-#pragma unroll
-          for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int J = 0; J < 3; ++J) z += Wg[3 * i + J] * tangent_entry(o, i, J, k, L);
-          Z[3 * k + L] = z;
-        }
+      cotangent_contract(o, Wg, Z);
       // parent-coordinate form Z J0^-T, rows padded to 4
+      double* rec = out + p * kZRec;
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
+      for (int k = 0; k < 3; ++k) {
 #pragma unroll
         for (int m = 0; m < 3; ++m)
-          s[12 * pass + 4 * k + m] = Z[3 * k] * Jinv[3 * m] + Z[3 * k + 1] * Jinv[3 * m + 1] + Z[3 * k + 2] * Jinv[3 * m + 2];
+          rec[4 * k + m] = Z[3 * k] * Jinv[3 * m] + Z[3 * k + 1] * Jinv[3 * m + 1] + Z[3 * k + 2] * Jinv[3 * m + 2];
+        rec[4 * k + 3] = 0.0;
+      }
     }
     if (gacc) {
       for (int th = 0; th < 5; ++th) {
@@ -74,37 +71,24 @@ __global__ __launch_bounds__(64) void k_vjp(AsmArgs a, const double* w, double* 
         double c = 0.0;
 #pragma unroll
         for (int t = 0; t < 9; ++t) c += Wg[t] * o.P[t];
-        atomicAdd(&red[th], c);
+        part[th] = c;
       }
     }
   }
-  __syncthreads();
-  for (int t = lane; t < TE * NEN; t += 64) {
-    const int el = t / NEN, al = t % NEN;
-    const int64_t ge = e0 + el;
-    if (ge >= a.n_elem) continue;
-    double scd[4];
-    element_scales<Rule>(a, ge, scd);
-    const int64_t c = coef_of<Rule>(a.conn + ge * Rule::NPN, al);
-    for (int pass = 0; pass < 2; ++pass) {
-      double* out = pass == 0 ? gq : gqd;
-      if (!out) continue;
-      double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-      sfor<0, NQ>([&](auto qc) __attribute__((always_inline)) {
-        constexpr int q = decltype(qc)::value;
-        const double* s = lds + (el * NQ + q) * 24 + 12 * pass;
-        const double d0 = Rule::dN_rt(q, al, 0), d1 = Rule::dN_rt(q, al, 1), d2 = Rule::dN_rt(q, al, 2);
-        g0 += s[0] * d0 + s[1] * d1 + s[2] * d2;
-        g1 += s[4] * d0 + s[5] * d1 + s[6] * d2;
-        g2 += s[8] * d0 + s[9] * d1 + s[10] * d2;
-      });
-      const double sa = scd[al % 4];
-      unsafeAtomicAdd(out + 3 * c, g0 * sa);
-      unsafeAtomicAdd(out + 3 * c + 1, g1 * sa);
-      unsafeAtomicAdd(out + 3 * c + 2, g2 * sa);
-    }
+  if (!gacc) return;
+  // workgroup sums of the five partials: one float64 atomic per partial and workgroup
+#pragma unroll
+  for (int th = 0; th < 5; ++th) {
+    double v = part[th];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][th] = v;
   }
-  if (gacc && lane < 5) unsafeAtomicAdd(gacc + lane, red[lane]);
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    double v = 0.0;
+    for (int wv = 0; wv < kVjpThreads / 64; ++wv) v += red[wv][threadIdx.x];
+    atomicAdd(gacc + threadIdx.x, v);
+  }
 }
 
 __global__ void k_zero5(double* p) {
@@ -130,34 +114,40 @@ __global__ void k_vjp_finalize(const double* gacc, int kind, double E, double nu
   gparam[4] = gacc[4];
 }
 
-template <class Rule, int TE>
-int launch_vjp_rule(const AsmArgs& a0, const double* w, double* gq, double* gqd, double* gacc, hipStream_t s) {
-  AsmArgs a = a0;
-  const int64_t tiles = (a.n_elem + TE - 1) / TE;
-  if (tiles > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
-  a.n_tiles = (int)tiles;
-  if (tiles > 0) hipLaunchKernelGGL((k_vjp<Rule, TE>), dim3(a.n_tiles), dim3(64), 0, s, a, w, gq, gqd, gacc);
+template <class Rule>
+int launch_vjp_stage(const AsmArgs& a, const double* w, double* zq, double* zqd, double* gacc, hipStream_t s) {
+  const int64_t npts = a.n_elem * Rule::NQ;
+  const int64_t blocks = (npts + kVjpThreads - 1) / kVjpThreads;
+  if (blocks > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
+  if (blocks > 0)
+    hipLaunchKernelGGL((k_vjp_stage<Rule>), dim3((unsigned)blocks), dim3(kVjpThreads), 0, s, a, w, zq, zqd, gacc);
   TLFEA_HIP_CHECK(hipGetLastError());
   return TLFEA_OK;
 }
 
 }  // namespace
 
-int launch_vjp(const Mesh& m, const double* q, const double* qdot, const double* w, double* gq, double* gqdot,
+int launch_vjp(Mesh& m, const double* q, const double* qdot, const double* w, double* gq, double* gqdot,
                double* gparam, hipStream_t s) {
   AsmArgs a = make_args(m, q, qdot, nullptr, nullptr, 1.0, 0.0);
   int rc;
-  if (gq && (rc = launch_zero(gq, m.n_dof, s))) return rc;
-  if (gqdot && (rc = launch_zero(gqdot, m.n_dof, s))) return rc;
+  const size_t set = (size_t)m.n_elem * m.n_qp * kZRec * sizeof(double);
+  // the Zhat records live in the mesh's work buffer: it no longer holds assembly records
+  if ((gq || gqdot) && (rc = ensure_stage(m, set * ((gq ? 1 : 0) + (gqdot ? 1 : 0))))) return rc;
+  m.staged = 0;
+  double* zq = gq ? (double*)m.d_stage : nullptr;
+  double* zqd = gqdot ? (double*)m.d_stage + (gq ? set / sizeof(double) : 0) : nullptr;
   double* gacc = gparam ? m.d_vjp_acc : nullptr;
   if (gacc) {
     hipLaunchKernelGGL(k_zero5, dim3(1), dim3(64), 0, s, gacc);
     TLFEA_HIP_CHECK(hipGetLastError());
   }
-  if (m.elem_type == TLFEA_T10) rc = launch_vjp_rule<RuleT10, 12>(a, w, gq, gqdot, gacc, s);
-  else if (m.gl[0] == 3) rc = launch_vjp_rule<RuleAncf<3, 3, 2>, 3>(a, w, gq, gqdot, gacc, s);
-  else rc = launch_vjp_rule<RuleAncf<4, 4, 3>, 1>(a, w, gq, gqdot, gacc, s);
+  if (m.elem_type == TLFEA_T10) rc = launch_vjp_stage<RuleT10>(a, w, zq, zqd, gacc, s);
+  else if (m.gl[0] == 3) rc = launch_vjp_stage<RuleAncf<3, 3, 2>>(a, w, zq, zqd, gacc, s);
+  else rc = launch_vjp_stage<RuleAncf<4, 4, 3>>(a, w, zq, zqd, gacc, s);
   if (rc) return rc;
+  if (gq && (rc = launch_force_gather_f64(m, zq, gq, s))) return rc;
+  if (gqdot && (rc = launch_force_gather_f64(m, zqd, gqdot, s))) return rc;
   if (gparam) {
     hipLaunchKernelGGL(k_vjp_finalize, dim3(1), dim3(64), 0, s, gacc, m.material, m.params[0], m.params[1], gparam);
     TLFEA_HIP_CHECK(hipGetLastError());

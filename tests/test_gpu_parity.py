@@ -182,7 +182,19 @@ def test_runtime_flags_and_errors():
     with pytest.raises(N.TlfeaError) as e:
         m2.tangent(q, None, out=torch.zeros(1, dtype=torch.float64, device="cuda"))
     assert e.value.status == -6
+    # the VJP's per-node sums run over the pattern's node ranges as well
+    with pytest.raises(N.TlfeaError) as e:
+        m2.vjp(q, None, q)
+    assert e.value.status == -6
     m2.close()
+    # the VJP reuses the work buffer: pass 2 alone then has nothing to reduce
+    m3 = make_mesh(wl, "fp64")
+    m3.assemble_points(q, None, 1.0, 1.0, True)
+    m3.vjp(q, None, q)
+    with pytest.raises(N.TlfeaError) as e:
+        m3.assemble_nodes(torch.empty(m3.n_dof, dtype=torch.float64, device="cuda"), None)
+    assert e.value.status == -1
+    m3.close()
     # degenerate reference element: a flat tetrahedron (coplanar corners)
     corners = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], dtype=float)
     X = np.vstack([corners, [(corners[a] + corners[b]) / 2 for a, b in W.T10_EDGES]])

@@ -282,13 +282,11 @@ __device__ __forceinline__ void load_slot(const R* p, Slot<R, WANT_K>& s) {
 
 // One point's contribution of a task (row i, component k of node a's
 // coefficient al): with the slot of the task's element at point Q and the
-// task's scaled parent gradient d,
+// task's scaled parent gradient d = dN_al(Q) (times the coefficient scale),
 //   t_n = sum_m d_m Ahat_imkn,  acc[b] += sum_n t_n dN_b,n(Q),  facc += Phat_ik d_k.
 template <class Rule, typename R, bool WANT_F, bool WANT_K, int Q, int NB>
-__device__ __forceinline__ void contract_point(const Slot<R, WANT_K>& s, int al, int k, R sc_al, R (&acc)[NB],
+__device__ __forceinline__ void contract_point(const Slot<R, WANT_K>& s, R d0, R d1, R d2, int k, R (&acc)[NB],
                                                R& facc) {
-  const R d0 = (R)Rule::dN_rt(Q, al, 0) * sc_al, d1 = (R)Rule::dN_rt(Q, al, 1) * sc_al,
-          d2 = (R)Rule::dN_rt(Q, al, 2) * sc_al;
   if constexpr (WANT_F) facc += (WANT_K ? s.v[9] : s.v[0]) * (k == 0 ? d0 : k == 1 ? d1 : d2);
   if constexpr (WANT_K) {
     R tn[3];
@@ -381,7 +379,6 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
     for (int j = pre[n] / TPI; j < pre[n + 1] / TPI; ++j) incn[j] = (uint8_t)n;
   __syncthreads();
   const int ntask = pre[nn];
-  const R* stage = (const R*)g.stage;
   // Tasks are ordered (node, incidence, kind, row, component): task t belongs
   // to incidence inc0 + t / TPI of the range.  The wave's chunk of an
   // iteration starting at task t0 covers incidences j0 .. j0 + ni - 1; lanes
@@ -392,13 +389,24 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
     j0_ = cw / TPI;
     ni_ = min(cw + 63, ntask - 1) / TPI - j0_ + 1;
   };
+  // the lane's copy pieces in a full chunk (record rr0, piece pp0); in a
+  // short chunk, pieces past its end become its last piece (ni - 1, NV - 1)
+  int rr0[KC], pp0[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    rr0[k] = (lane + 64 * k) / NV;
+    pp0[k] = lane + 64 * k - rr0[k] * NV;
+  }
+  // record addresses in 16-byte units (32 bits: checked on the host)
+  const V* stagev = reinterpret_cast<const V*>(g.stage);
+  constexpr uint32_t VPP = REC / PER;  // 16-byte pieces per point record
   // incidence entries an iteration needs (its copy pieces' and the lane's
   // own), fetched one iteration ahead
   auto fetch_inc = [&](int t0_, int32_t (&icp)[KC], int32_t& ime) __attribute__((always_inline)) {
     int j0_, ni_;
     chunk(t0_, j0_, ni_);
 #pragma unroll
-    for (int k = 0; k < KC; ++k) icp[k] = g.inc[inc0 + j0_ + min(lane + 64 * k, ni_ * NV - 1) / NV];
+    for (int k = 0; k < KC; ++k) icp[k] = g.inc[inc0 + j0_ + min(rr0[k], ni_ - 1)];
     ime = g.inc[inc0 + min(t0_ + tid, ntask - 1) / TPI];
   };
   int32_t icp[KC], ime;
@@ -408,20 +416,19 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
     const int t = min(t0 + tid, ntask - 1);
     int j0, ni;
     chunk(t0, j0, ni);
-    int64_t src[KC];
+    uint32_t src[KC];
     int dst[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-      const int c = min(lane + 64 * k, ni * NV - 1);
-      const int rr = c / NV, pp = c - rr * NV;
-      src[k] = (int64_t)(icp[k] >> 4) * NQ * REC + pp * PER;
-      dst[k] = rr * REC + pp * PER;
+      const bool in = rr0[k] < ni;
+      src[k] = (uint32_t)(icp[k] >> 4) * (NQ * VPP) + (uint32_t)(in ? pp0[k] : NV - 1);
+      dst[k] = in ? rr0[k] * REC + pp0[k] * PER : ni * REC - PER;
     }
     V buf[PD][KC];
     sfor<0, PD>([&](auto qc) __attribute__((always_inline)) {
       constexpr int q = decltype(qc)::value;
 #pragma unroll
-      for (int k = 0; k < KC; ++k) buf[q][k] = *reinterpret_cast<const V*>(stage + src[k] + q * REC);
+      for (int k = 0; k < KC; ++k) buf[q][k] = stagev[src[k] + q * VPP];
     });
     const int32_t packed = ime;
     if (t0 + (int)blockDim.x < ntask) fetch_inc(t0 + blockDim.x, icp, ime);
@@ -459,6 +466,19 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
     for (int b = 0; b < NB; ++b) acc[b] = R(0);
     R facc = R(0);
     if constexpr (UNROLL) {
+      // the task's parent gradients at all points: one row of the table
+      R dna[16];
+      {
+        using V4 = typename Vec4<R>::type;
+        constexpr int P4 = (int)(sizeof(V4) / sizeof(R));
+        const V4* rowv = reinterpret_cast<const V4*>(Rule::template rows<R>(al));
+#pragma unroll
+        for (int t = 0; t < 16 / P4; ++t) {
+          const V4 x = rowv[t];
+#pragma unroll
+          for (int u = 0; u < P4; ++u) dna[P4 * t + u] = x[u] * sc_al;
+        }
+      }
       sfor<0, NQ>([&](auto qc) __attribute__((always_inline)) {
         constexpr int q = decltype(qc)::value;
         wave_sync();  // every lane is done with the previous point's records
@@ -468,11 +488,11 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
         if constexpr (q + PD < NQ) {
 #pragma unroll
           for (int kk = 0; kk < KC; ++kk)
-            buf[q % PD][kk] = *reinterpret_cast<const V*>(stage + src[kk] + (q + PD) * REC);
+            buf[q % PD][kk] = stagev[src[kk] + (q + PD) * VPP];
         }
         Slot<R, WANT_K> sl;
         load_slot<R, WANT_K>(mine, sl);
-        contract_point<Rule, R, WANT_F, WANT_K, q, NB>(sl, al, k, sc_al, acc, facc);
+        contract_point<Rule, R, WANT_F, WANT_K, q, NB>(sl, dna[3 * q], dna[3 * q + 1], dna[3 * q + 2], k, acc, facc);
       });
     } else {
 #pragma unroll 1
@@ -487,7 +507,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
           if (q + PB < NQ) {
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk)
-              buf[x][kk] = *reinterpret_cast<const V*>(stage + src[kk] + (int64_t)(q + PB) * REC);
+              buf[x][kk] = stagev[src[kk] + (uint32_t)(q + PB) * VPP];
           }
           Slot<R, WANT_K> sl;
           load_slot<R, WANT_K>(mine, sl);
@@ -588,9 +608,17 @@ int launch_points_rule(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t
   return TLFEA_OK;
 }
 
+// pass 2 addresses records in 16-byte units with 32-bit offsets
+template <class Rule, typename R>
+bool records_addressable(int64_t n_elem, bool want_k) {
+  const int64_t pieces = (int64_t)Rule::NQ * (want_k ? kRecK : kRecF) * (int64_t)sizeof(R) / 16;
+  return n_elem * pieces < ((int64_t)1 << 32);
+}
+
 template <class Rule, typename R>
 int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals, bool accum, hipStream_t s) {
   const bool want_f = f != nullptr, want_k = vals != nullptr;
+  if (!records_addressable<Rule, R>(m.n_elem, want_k)) return TLFEA_ERR_TOO_LARGE;
   GatherArgs g{};
   g.ranges = m.d_ranges;
   g.inc_off = m.d_inc_off;

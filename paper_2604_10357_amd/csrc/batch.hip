@@ -96,6 +96,11 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
     for (int r = 0; r < m.n_ranges; ++r) ranges.push_back(BatchRange{i, m.h_ranges[r], m.h_ranges[r + 1]});
     max_vals = std::max(max_vals, m.max_range_values);
     b->inc_cap = std::max(b->inc_cap, (int)((m.max_range_inc + 15) / 16 * 16));
+    // pass 2 addresses a body's records in 16-byte units with 32-bit offsets
+    if (m.n_elem * m.n_qp * (int64_t)(tlfea::stage_record_bytes(b->precision) / 16) >= ((int64_t)1 << 32)) {
+      delete b;
+      return TLFEA_ERR_TOO_LARGE;
+    }
     b->meshes.push_back(meshes[i]);
   }
   if (ranges.size() > (size_t)INT32_MAX || b->n_blocks > INT32_MAX) { delete b; return TLFEA_ERR_TOO_LARGE; }

@@ -31,8 +31,31 @@ __device__ __forceinline__ void sfor(F&& f) {
   }
 }
 
+// Parent gradients of one shape function at every point of the T10 rule,
+// dN_a(q)_m at 3 q + m, padded to 16 values: one row per node, in the record
+// precision, fetched by a lane with a few vector loads.
+template <typename R>
+struct alignas(16) T10Rows {
+  R v[10][16];
+};
+template <typename R>
+constexpr T10Rows<R> make_t10_rows() {
+  T10Rows<R> t{};
+  for (int a = 0; a < 10; ++a)
+    for (int q = 0; q < 5; ++q)
+      for (int m = 0; m < 3; ++m) t.v[a][3 * q + m] = (R)kT10.dN[q][a][m];
+  return t;
+}
+static __constant__ T10Rows<float> c_t10_rows_f = make_t10_rows<float>();
+static __constant__ T10Rows<double> c_t10_rows_d = make_t10_rows<double>();
+
 struct RuleT10 {
   static constexpr int NEN = 10, NPN = 10, MC = 1, NQ = 5;
+  template <typename R>
+  __device__ static const R* rows(int a) {
+    if constexpr (sizeof(R) == 4) return c_t10_rows_f.v[a];
+    else return c_t10_rows_d.v[a];
+  }
   static constexpr double dN(int q, int a, int m) { return kT10.dN[q][a][m]; }
   __device__ static double dN_rt(int q, int a, int m) { return c_t10.dN[q][a][m]; }
   __device__ static double w_rt(int q) { return c_t10.w[q]; }

@@ -156,6 +156,78 @@ def test_config5_sampled(precision):
     m.close()
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_config3_sampled(precision):
+    """The 256 x 256 ANCF3443 plate (65,536 elements, 3x3x2 rule) at full size in
+    the benchmark's launch: rows of sampled nodes (all 12 coefficient rows)
+    against the oracle."""
+    print(f"[gpu] config3 sampled {precision}", flush=True)
+    wl = W.config3()
+    m = make_mesh(wl, precision)
+    h = 1e-3
+    f, vals = m.assemble(cuda(wl.q), cuda(wl.qdot), h, 1.0)
+    ro, cols = m.csr_pattern(on_device=False)
+    fh, vh = f.cpu().numpy(), vals.cpu().numpy()
+    n_nodes = int(wl.mesh.conn.max()) + 1
+    rng = np.random.default_rng(33)
+    # corners, an edge node, the centre and random interior nodes
+    nodes = np.concatenate([[0, 256, n_nodes - 1, 128, n_nodes // 2], rng.choice(n_nodes, 12, replace=False)])
+    om = oracle.Mesh.of(wl.mesh)
+    f_ref, rows_ref, rows = oracle_rows(om, oracle.material_of(wl.material), wl, h, 1.0, nodes)
+    got = dense_rows(ro.numpy(), cols.numpy(), vh, rows)
+    fmax = np.abs(f_ref[rows]).max()
+    kmax = max(max(abs(v) for v in r.values()) for r in rows_ref.values())
+    ef = np.abs(fh[rows] - f_ref[rows]).max() / fmax
+    ek = 0.0
+    for r in rows:
+        assert set(got[r].keys()) == set(rows_ref[r].keys())
+        for c, v in rows_ref[r].items():
+            ek = max(ek, abs(got[r][c] - v) / kmax)
+    print(f"  config3 {precision}: sampled f {ef:.2e}  K {ek:.2e}", flush=True)
+    assert ef <= TOL[precision] and ek <= TOL[precision]
+    m.close()
+
+
+@pytest.mark.gpu
+def test_config4_full_batch():
+    """All 512 cubes (about 1.7 M elements, mixed precision) in one graph-captured
+    launch pair: sampled bodies against the oracle, every body against the
+    per-body loop."""
+    from paper_2604_10357_amd.api import TLBatch
+    print("[gpu] config4 full batch", flush=True)
+    wls = W.config4()
+    meshes = [make_mesh(wl, "mixed") for wl in wls]
+    b = TLBatch(meshes)
+    q = cuda(np.concatenate([wl.q for wl in wls]))
+    qd = cuda(np.concatenate([wl.qdot for wl in wls]))
+    hs = np.full(len(wls), 1e-3)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        f, vals = b.assemble(q, qd, cuda(hs))
+        f2, vals2 = b.assemble(q, qd, cuda(hs))  # graph replay
+        fl, vl = b.assemble(q, qd, cuda(hs), loop=True)
+    stream.synchronize()
+    fh, vh = f.cpu().numpy(), vals.cpu().numpy()
+    assert torch.equal(f, f2) and torch.equal(vals, vals2)
+    assert np.abs(fl.cpu().numpy() - fh).max() <= 1e-13 * np.abs(fh).max()
+    assert np.abs(vl.cpu().numpy() - vh).max() <= 1e-13 * np.abs(vh).max()
+    rng = np.random.default_rng(44)
+    for k in sorted(set([0, len(wls) - 1] + rng.choice(len(wls), 6, replace=False).tolist())):
+        wl = wls[k]
+        d0, d1 = b.dof_off[k], b.dof_off[k + 1]
+        z0, z1 = b.nnz_off[k], b.nnz_off[k + 1]
+        om = oracle.Mesh.of(wl.mesh)
+        f_ref, v_ref = oracle.assemble(om, oracle.material_of(wl.material), wl.q, wl.qdot, hs[k], 1.0)
+        ef = rel_err(fh[d0:d1], f_ref)[0]
+        ek = rel_err(vh[z0:z1], v_ref)[0]
+        print(f"  body {k}: {wl.mesh.n_elem} elements, f {ef:.2e} K {ek:.2e}", flush=True)
+        assert ef <= TOL["mixed"] and ek <= TOL["mixed"]
+    b.close()
+    for m in meshes:
+        m.close()
+
+
 def test_runtime_flags_and_errors():
     from paper_2604_10357_amd import _native as N
     wl = W.config1()

@@ -312,9 +312,18 @@ __device__ __forceinline__ void contract_point(const Slot<R, WANT_K>& s, R d0, R
 // registers while a point is contracted.
 constexpr int chunk_incidences(int tpi) { return (tpi + 62) / tpi + 1; }
 
+// Float32 tangent records of short rules skip the LDS copy: a lane's 10-value
+// slot always lies in three aligned 16-byte pieces of its record, which the lane
+// loads itself for all points at once.
+template <class Rule, typename R, bool WANT_K>
+constexpr bool direct_slots() {
+  return WANT_K && sizeof(R) == 4 && Rule::NQ <= 6;
+}
+
 template <class Rule, typename R, bool WANT_K>
 constexpr size_t wave_buf_bytes() {
-  return (size_t)chunk_incidences(9 * Rule::MC) * (WANT_K ? kRecK : kRecF) * sizeof(R);
+  return direct_slots<Rule, R, WANT_K>() ? 0
+                                         : (size_t)chunk_incidences(9 * Rule::MC) * (WANT_K ? kRecK : kRecF) * sizeof(R);
 }
 
 // The same with a run-time point index q (long rules); q is uniform across the
@@ -354,6 +363,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   static_assert(NQ % PB == 0, "point blocks must tile the rule");
   constexpr int PD = UNROLL ? (sizeof(R) == 4 ? NQ : 3) : PB;  // points whose pieces are in flight
   constexpr int NB = WANT_K ? NEN : 1;
+  constexpr bool DIRECT = direct_slots<Rule, R, WANT_K>();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
   // LDS: incidence -> node table, wave record buffers, CSR segment + forces
   uint8_t* incn = smem;
@@ -405,8 +415,10 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   auto fetch_inc = [&](int t0_, int32_t (&icp)[KC], int32_t& ime) __attribute__((always_inline)) {
     int j0_, ni_;
     chunk(t0_, j0_, ni_);
+    if constexpr (!DIRECT) {
 #pragma unroll
-    for (int k = 0; k < KC; ++k) icp[k] = g.inc[inc0 + j0_ + min(rr0[k], ni_ - 1)];
+      for (int k = 0; k < KC; ++k) icp[k] = g.inc[inc0 + j0_ + min(rr0[k], ni_ - 1)];
+    }
     ime = g.inc[inc0 + min(t0_ + tid, ntask - 1) / TPI];
   };
   int32_t icp[KC], ime;
@@ -424,12 +436,14 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
       src[k] = (uint32_t)(icp[k] >> 4) * (NQ * VPP) + (uint32_t)(in ? pp0[k] : NV - 1);
       dst[k] = in ? rr0[k] * REC + pp0[k] * PER : ni * REC - PER;
     }
-    V buf[PD][KC];
-    sfor<0, PD>([&](auto qc) __attribute__((always_inline)) {
-      constexpr int q = decltype(qc)::value;
+    V buf[DIRECT ? 1 : PD][KC];
+    if constexpr (!DIRECT) {
+      sfor<0, PD>([&](auto qc) __attribute__((always_inline)) {
+        constexpr int q = decltype(qc)::value;
 #pragma unroll
-      for (int k = 0; k < KC; ++k) buf[q][k] = stagev[src[k] + q * VPP];
-    });
+        for (int k = 0; k < KC; ++k) buf[q][k] = stagev[src[k] + q * VPP];
+      });
+    }
     const int32_t packed = ime;
     if (t0 + (int)blockDim.x < ntask) fetch_inc(t0 + blockDim.x, icp, ime);
     const int n = incn[t / TPI];
@@ -465,6 +479,17 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = R(0);
     R facc = R(0);
+    // DIRECT: the lane's slot s = 3 i + k sits at value 10 s of each point
+    // record, inside pieces floor(10 s / 4) .. + 2, shifted by 0 (s even) or 2
+    V own[DIRECT ? NQ : 1][3];
+    const bool odd_slot = (3 * i + k) & 1;
+    if constexpr (DIRECT) {
+      const uint32_t p0 = (uint32_t)(packed >> 4) * (NQ * VPP) + (uint32_t)((kSlot * (3 * i + k)) >> 2);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) own[q][j] = stagev[p0 + q * VPP + j];
+    }
     if constexpr (UNROLL) {
       // the task's parent gradients at all points: one row of the table
       R dna[16];
@@ -481,17 +506,25 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
       }
       sfor<0, NQ>([&](auto qc) __attribute__((always_inline)) {
         constexpr int q = decltype(qc)::value;
-        wave_sync();  // every lane is done with the previous point's records
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk) *reinterpret_cast<V*>(wbuf + dst[kk]) = buf[q % PD][kk];
-        wave_sync();
-        if constexpr (q + PD < NQ) {
-#pragma unroll
-          for (int kk = 0; kk < KC; ++kk)
-            buf[q % PD][kk] = stagev[src[kk] + (q + PD) * VPP];
-        }
         Slot<R, WANT_K> sl;
-        load_slot<R, WANT_K>(mine, sl);
+        if constexpr (DIRECT) {
+#pragma unroll
+          for (int x = 0; x < kSlot; ++x) {
+            const R lo = own[q][x >> 2][x & 3], hi = own[q][(x + 2) >> 2][(x + 2) & 3];
+            sl.v[x] = odd_slot ? hi : lo;
+          }
+        } else {
+          wave_sync();  // every lane is done with the previous point's records
+#pragma unroll
+          for (int kk = 0; kk < KC; ++kk) *reinterpret_cast<V*>(wbuf + dst[kk]) = buf[q % PD][kk];
+          wave_sync();
+          if constexpr (q + PD < NQ) {
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk)
+              buf[q % PD][kk] = stagev[src[kk] + (q + PD) * VPP];
+          }
+          load_slot<R, WANT_K>(mine, sl);
+        }
         contract_point<Rule, R, WANT_F, WANT_K, q, NB>(sl, dna[3 * q], dna[3 * q + 1], dna[3 * q + 2], k, acc, facc);
       });
     } else {

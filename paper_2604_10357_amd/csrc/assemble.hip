@@ -312,18 +312,31 @@ __device__ __forceinline__ void contract_point(const Slot<R, WANT_K>& s, R d0, R
 // registers while a point is contracted.
 constexpr int chunk_incidences(int tpi) { return (tpi + 62) / tpi + 1; }
 
-// Float32 tangent records of short rules skip the LDS copy: a lane's 10-value
-// slot always lies in three aligned 16-byte pieces of its record, which the lane
-// loads itself for all points at once.
+// Float32 tangent records of short rules can be read two ways: through the
+// LDS copy, or by the lane itself (its 10-value slot always lies in three
+// aligned 16-byte pieces of the record), for all points at once.  The first
+// kStagedPoints points take the LDS copy; splitting the points between the two
+// paths did not beat reading them all directly (the default, 0).
+#ifndef TLFEA_STAGED_POINTS
+#define TLFEA_STAGED_POINTS 0
+#endif
+constexpr int kStagedPoints = TLFEA_STAGED_POINTS;
+
 template <class Rule, typename R, bool WANT_K>
 constexpr bool direct_slots() {
   return WANT_K && sizeof(R) == 4 && Rule::NQ <= 6;
 }
+// points of a rule that go through the LDS copy
+template <class Rule, typename R, bool WANT_K>
+constexpr int staged_points() {
+  return direct_slots<Rule, R, WANT_K>() ? (kStagedPoints < Rule::NQ ? kStagedPoints : Rule::NQ) : Rule::NQ;
+}
 
 template <class Rule, typename R, bool WANT_K>
 constexpr size_t wave_buf_bytes() {
-  return direct_slots<Rule, R, WANT_K>() ? 0
-                                         : (size_t)chunk_incidences(9 * Rule::MC) * (WANT_K ? kRecK : kRecF) * sizeof(R);
+  return staged_points<Rule, R, WANT_K>() == 0
+             ? 0
+             : (size_t)chunk_incidences(9 * Rule::MC) * (WANT_K ? kRecK : kRecF) * sizeof(R);
 }
 
 // The same with a run-time point index q (long rules); q is uniform across the
@@ -364,6 +377,8 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   constexpr int PD = UNROLL ? (sizeof(R) == 4 ? NQ : 3) : PB;  // points whose pieces are in flight
   constexpr int NB = WANT_K ? NEN : 1;
   constexpr bool DIRECT = direct_slots<Rule, R, WANT_K>();
+  constexpr int NS = staged_points<Rule, R, WANT_K>();  // points through the LDS copy (DIRECT: the first NS)
+  constexpr int PDS = DIRECT ? (NS > 0 ? NS : 1) : PD;     // staged points in flight
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
   // LDS: incidence -> node table, wave record buffers, CSR segment + forces
   uint8_t* incn = smem;
@@ -415,7 +430,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   auto fetch_inc = [&](int t0_, int32_t (&icp)[KC], int32_t& ime) __attribute__((always_inline)) {
     int j0_, ni_;
     chunk(t0_, j0_, ni_);
-    if constexpr (!DIRECT) {
+    if constexpr (NS > 0) {
 #pragma unroll
       for (int k = 0; k < KC; ++k) icp[k] = g.inc[inc0 + j0_ + min(rr0[k], ni_ - 1)];
     }
@@ -436,9 +451,9 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
       src[k] = (uint32_t)(icp[k] >> 4) * (NQ * VPP) + (uint32_t)(in ? pp0[k] : NV - 1);
       dst[k] = in ? rr0[k] * REC + pp0[k] * PER : ni * REC - PER;
     }
-    V buf[DIRECT ? 1 : PD][KC];
-    if constexpr (!DIRECT) {
-      sfor<0, PD>([&](auto qc) __attribute__((always_inline)) {
+    V buf[PDS][KC];
+    if constexpr (NS > 0) {
+      sfor<0, PDS>([&](auto qc) __attribute__((always_inline)) {
         constexpr int q = decltype(qc)::value;
 #pragma unroll
         for (int k = 0; k < KC; ++k) buf[q][k] = stagev[src[k] + q * VPP];
@@ -481,14 +496,14 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
     R facc = R(0);
     // DIRECT: the lane's slot s = 3 i + k sits at value 10 s of each point
     // record, inside pieces floor(10 s / 4) .. + 2, shifted by 0 (s even) or 2
-    V own[DIRECT ? NQ : 1][3];
+    V own[DIRECT && NQ > NS ? NQ - NS : 1][3];
     const bool odd_slot = (3 * i + k) & 1;
-    if constexpr (DIRECT) {
+    if constexpr (DIRECT && NQ > NS) {
       const uint32_t p0 = (uint32_t)(packed >> 4) * (NQ * VPP) + (uint32_t)((kSlot * (3 * i + k)) >> 2);
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
+      for (int q = NS; q < NQ; ++q)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) own[q][j] = stagev[p0 + q * VPP + j];
+        for (int j = 0; j < 3; ++j) own[q - NS][j] = stagev[p0 + q * VPP + j];
     }
     if constexpr (UNROLL) {
       // the task's parent gradients at all points: one row of the table
@@ -507,21 +522,21 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
       sfor<0, NQ>([&](auto qc) __attribute__((always_inline)) {
         constexpr int q = decltype(qc)::value;
         Slot<R, WANT_K> sl;
-        if constexpr (DIRECT) {
+        if constexpr (DIRECT && q >= NS) {
 #pragma unroll
           for (int x = 0; x < kSlot; ++x) {
-            const R lo = own[q][x >> 2][x & 3], hi = own[q][(x + 2) >> 2][(x + 2) & 3];
+            const R lo = own[q - NS][x >> 2][x & 3], hi = own[q - NS][(x + 2) >> 2][(x + 2) & 3];
             sl.v[x] = odd_slot ? hi : lo;
           }
         } else {
           wave_sync();  // every lane is done with the previous point's records
 #pragma unroll
-          for (int kk = 0; kk < KC; ++kk) *reinterpret_cast<V*>(wbuf + dst[kk]) = buf[q % PD][kk];
+          for (int kk = 0; kk < KC; ++kk) *reinterpret_cast<V*>(wbuf + dst[kk]) = buf[q % PDS][kk];
           wave_sync();
-          if constexpr (q + PD < NQ) {
+          if constexpr (q + PDS < NS) {
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk)
-              buf[q % PD][kk] = stagev[src[kk] + (q + PD) * VPP];
+              buf[q % PDS][kk] = stagev[src[kk] + (q + PDS) * VPP];
           }
           load_slot<R, WANT_K>(mine, sl);
         }

@@ -189,7 +189,12 @@ int tlfea_assemble_accumulate(tlfea_mesh_t mesh, const double* d_q, const double
  *     tlfea_assemble_points of the same mesh left; returns TLFEA_ERR_INVALID
  *     if that does not exist, lacks the tangent or used another precision.
  * tlfea_assemble_ex(...) is exactly tlfea_assemble_points(..., 1, s) followed
- * by tlfea_assemble_nodes(..., 0, s). */
+ * by tlfea_assemble_nodes(..., 0, s).
+ * Reproducibility: repeated calls on the same inputs agree to rounding (a few
+ * units in the last place of the largest value), not bit for bit, because each
+ * node range adds its contributions in the order its waves deliver them; an
+ * atomic scatter per entry (Sec. 4.3, Eq. atomic_scatter; Sec. 4.4.2) behaves
+ * the same way. */
 int tlfea_assemble_points(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double alpha,
                           double beta, int32_t want_tangent, void* stream);
 int tlfea_assemble_nodes(tlfea_mesh_t mesh, double* d_f, double* d_vals, int32_t accumulate,

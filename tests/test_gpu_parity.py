@@ -209,7 +209,9 @@ def test_config4_full_batch():
         fl, vl = b.assemble(q, qd, cuda(hs), loop=True)
     stream.synchronize()
     fh, vh = f.cpu().numpy(), vals.cpu().numpy()
-    assert torch.equal(f, f2) and torch.equal(vals, vals2)
+    # The per-range LDS sums take contributions from several waves in arrival
+    # order, so repeated calls agree to rounding, not bit for bit.
+    assert rel_err(f2.cpu().numpy(), fh)[0] <= 1e-13 and rel_err(vals2.cpu().numpy(), vh)[0] <= 1e-13
     assert np.abs(fl.cpu().numpy() - fh).max() <= 1e-13 * np.abs(fh).max()
     assert np.abs(vl.cpu().numpy() - vh).max() <= 1e-13 * np.abs(vh).max()
     rng = np.random.default_rng(44)

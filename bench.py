@@ -54,16 +54,19 @@ def mesh_bytes(wl, nnz, affine=True):
     return algorithmic_bytes(m.n_elem, m.n_dof, nnz, 4, 80 if affine else 80 * nq, 16)
 
 
-def measured_traffic(precision):
+def measured_traffic(precision, shape):
     """HBM bytes per call of the two kernels from the committed counter report
     (FETCH_SIZE / WRITE_SIZE calibrated on a 1 GiB copy), or None when the
-    report is missing, is for another precision, or the kernels changed since."""
+    report is missing, is for another precision or pass-2 launch shape, or the
+    kernels changed since."""
     if precision != "mixed" or not os.path.exists(TRAFFIC_FILE):
         return None
     from paper_2604_10357_amd import pmc
     with open(TRAFFIC_FILE) as fh:
         rep = json.load(fh)
     if rep.get("kernel_source_sha256") != pmc.kernel_source_hash():
+        return None
+    if rep.get("gather_shape", pmc.DEFAULT_SHAPE) != shape:
         return None
     ks = rep["kernels"]
     names = [k for k in ks if k.startswith("k_stage_tile<RuleT10, float>") or
@@ -156,6 +159,23 @@ WORKLOADS = {
 }
 
 
+def autotune(args, obj, tune):
+    """Pass-2 launch shape: the library's autotuner (run once, before any timed
+    call), unless --gather-shape sets one or --no-autotune keeps the default;
+    returns what was used."""
+    if args.gather_shape:
+        obj.set_gather_shape(*args.gather_shape)
+        return {"autotuned": False, "gather_shape": obj.gather_shape()[0]}
+    if args.no_autotune:
+        return {"autotuned": False, "gather_shape": obj.gather_shape()[0]}
+    t0 = time.perf_counter()
+    shape, ms, _, _ = tune()
+    out = {"autotuned": True, "gather_shape": shape, "tuned_ms_per_call": ms,
+           "autotune_s": time.perf_counter() - t0}
+    print(f"[bench] autotuned pass-2 shape {shape} ({ms:.3f} ms per call)", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_mesh(args, torch, wl, wname):
     from paper_2604_10357_amd.api import TLMesh
 
@@ -171,6 +191,7 @@ def bench_mesh(args, torch, wl, wname):
     torch.cuda.synchronize()
     print(f"[bench] {wname} setup {time.perf_counter() - t_setup:.1f} s: {n_el} elements, {n_dof} dof, nnz {nnz}",
           file=sys.stderr, flush=True)
+    tuning = autotune(args, mesh, lambda: mesh.autotune(q, qd, h, f, vals, reps=5))
 
     def step():
         mesh.assemble(q, qd, h, 1.0, f, vals)
@@ -197,7 +218,7 @@ def bench_mesh(args, torch, wl, wname):
     # algorithmic bytes are set against the time of the whole call
     B = mesh_bytes(wl, nnz)
     achieved = B / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.precision) if wname == "t10_beam" else None
+    traffic = measured_traffic(args.precision, tuning["gather_shape"]) if wname == "t10_beam" else None
     kname = "T10" if wl.mesh.elem_type == 1 else "ANCF3443"
     mat = "mooney_rivlin" if wl.material.kind == 2 else "svk"
     if wl.material.kv_eta or wl.material.kv_lambda:
@@ -217,6 +238,7 @@ def bench_mesh(args, torch, wl, wname):
         "data": "synthetic",
         "config": {"workload": WORKLOADS[wname][1], "elements": n_el, "dof": n_dof, "nnz": nnz,
                    "precision": args.precision, "material": mat, "h": h},
+        "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"k_stage_tile + k_gather ({kname}, f + K)", "kernel_ms": ms,
@@ -280,7 +302,9 @@ def bench_batched(args, torch):
     n_el = sum(wl.mesh.n_elem for wl in wls)
     B = sum(mesh_bytes(wl, m.nnz) for wl, m in zip(wls, meshes))
     s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
+        tuning = autotune(args, b, lambda: b.autotune(q, qd, hs, f, vals, reps=5))
         for _ in range(args.warmup):
             b.assemble(q, qd, hs, f, vals)
         ms = time_calls(lambda: b.assemble(q, qd, hs, f, vals), args.steps, torch)
@@ -296,6 +320,7 @@ def bench_batched(args, torch):
         "vs_baseline": None, "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": "t10_cubes_x512_batched", "bodies": len(wls), "elements": n_el, "dof": int(nd),
                    "nnz": int(nz), "precision": args.precision},
+        "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_stage_batch + k_gather_batch (one graph)", "kernel_ms": ms,
@@ -318,6 +343,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="t10_beam", choices=list(WORKLOADS) + ["batched"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--gather-shape", type=int, nargs=3, metavar=("WAVES", "RANGE_TASKS", "RANGE_VALUES"))
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU: this library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)

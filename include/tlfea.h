@@ -219,6 +219,42 @@ int tlfea_internal_force_vjp(tlfea_mesh_t mesh, const double* d_q, const double*
 int tlfea_get_runtime_flags(tlfea_mesh_t mesh, uint32_t* flags);
 
 /* ---------------------------------------------------------------------------
+ * Launch shape of the per-node pass and its autotuning.
+ * Not a step of the method: the shape decides how the nodes are cut into
+ * ranges (each range is one workgroup whose CSR rows are one contiguous
+ * segment held in LDS) and how many waves work on a range.  Every shape gives
+ * the same result up to rounding order.  The default is {4, 768, 4096}
+ * (environment TLFEA_GATHER_WAVES / TLFEA_RANGE_TASKS / TLFEA_RANGE_VALUES
+ * override it when the pattern is built).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t waves;        /* waves of 64 lanes per workgroup, 1 .. 8 */
+  int32_t range_tasks;  /* cap on a range's tasks (9 per T10 incidence, 36 per ANCF) */
+  int32_t range_values; /* cap on a range's CSR values + force rows, in float64 */
+} tlfea_gather_shape;
+
+/* Re-cut the mesh's node ranges for `shape` (a single node may exceed the
+ * caps; a range never exceeds 64 nodes).  Needs the pattern
+ * (TLFEA_ERR_NO_PATTERN); TLFEA_ERR_UNSUPPORTED, with the mesh unchanged, if a
+ * range would need more than 96 KiB of LDS.  Synchronises the device. */
+int tlfea_mesh_set_gather_shape(tlfea_mesh_t mesh, const tlfea_gather_shape* shape);
+/* Current shape and number of ranges (either pointer may be NULL). */
+int tlfea_mesh_get_gather_shape(tlfea_mesh_t mesh, tlfea_gather_shape* shape, int64_t* n_ranges);
+
+/* Time tlfea_assemble(mesh, d_q, d_qdot, h, d_f, d_vals) for each shape of
+ * the grid waves {2,4,8} x range_tasks {384,768,1536} x range_values
+ * {2048,4096,8192} and for the shape in use (`reps` timed calls after one
+ * warm-up, HIP events on `stream`), keep the fastest if it beats the shape in
+ * use by at least 5 % (else keep that one), and leave the kept shape's result
+ * in d_f / d_vals.  Shapes that do not fit are skipped.  chosen / ms_per_call (may be NULL) receive
+ * the shape and its mean time per call.  reps in 1 .. 1000.  Synchronises;
+ * meant to be called once, before a run of assemblies.  On an error the
+ * previous shape is restored. */
+int tlfea_mesh_autotune(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double h,
+                        double* d_f, double* d_vals, int32_t reps, void* stream,
+                        tlfea_gather_shape* chosen, float* ms_per_call);
+
+/* ---------------------------------------------------------------------------
  * Batched assembly of many independent bodies in one launch.
  * Each body keeps its own CSR (int32 within a body).  Body b owns
  * q/qdot/f[dof_off[b] .. dof_off[b+1]) and vals[nnz_off[b] .. nnz_off[b+1]).
@@ -240,6 +276,19 @@ int tlfea_batch_assemble(tlfea_batch_t batch, const double* d_q, const double* d
 /* Same as a loop of tlfea_assemble calls, one launch per body (reference path). */
 int tlfea_batch_assemble_loop(tlfea_batch_t batch, const double* d_q, const double* d_qdot,
                               const double* d_h, double* d_f, double* d_vals, void* stream);
+
+/* The batch's own pass-2 launch shape (the bodies' shapes are not changed):
+ * set, get and autotune as for a mesh, over the concatenated ranges of all
+ * bodies.  The batch starts with the first body's shape.  A new shape drops
+ * the captured graph of tlfea_batch_assemble (it is captured again at the
+ * next call).  tlfea_batch_autotune times the uncaptured launch pair of
+ * tlfea_batch_assemble on `stream` and leaves the fastest shape's result in
+ * d_f / d_vals. */
+int tlfea_batch_set_gather_shape(tlfea_batch_t batch, const tlfea_gather_shape* shape);
+int tlfea_batch_get_gather_shape(tlfea_batch_t batch, tlfea_gather_shape* shape, int64_t* n_ranges);
+int tlfea_batch_autotune(tlfea_batch_t batch, const double* d_q, const double* d_qdot, const double* d_h,
+                         double* d_f, double* d_vals, int32_t reps, void* stream, tlfea_gather_shape* chosen,
+                         float* ms_per_call);
 
 #ifdef __cplusplus
 }

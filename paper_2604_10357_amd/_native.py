@@ -27,6 +27,8 @@ EXPORTED = [
     "tlfea_get_slot_map", "tlfea_internal_force", "tlfea_tangent", "tlfea_tangent_ex", "tlfea_assemble",
     "tlfea_assemble_ex", "tlfea_assemble_accumulate", "tlfea_assemble_points", "tlfea_assemble_nodes", "tlfea_internal_force_vjp", "tlfea_get_runtime_flags", "tlfea_batch_create",
     "tlfea_batch_destroy", "tlfea_batch_offsets", "tlfea_batch_assemble", "tlfea_batch_assemble_loop",
+    "tlfea_mesh_set_gather_shape", "tlfea_mesh_get_gather_shape", "tlfea_mesh_autotune",
+    "tlfea_batch_set_gather_shape", "tlfea_batch_get_gather_shape", "tlfea_batch_autotune",
 ]
 
 
@@ -45,6 +47,13 @@ class MeshDesc(ctypes.Structure):
         ("kv_lambda", ctypes.c_double),
         ("precision", ctypes.c_int32),
     ]
+
+
+class GatherShape(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_int32), ("range_tasks", ctypes.c_int32), ("range_values", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"waves": self.waves, "range_tasks": self.range_tasks, "range_values": self.range_values}
 
 
 class TlfeaError(RuntimeError):
@@ -92,6 +101,12 @@ def lib() -> ctypes.CDLL:
         "tlfea_batch_offsets": ([vp, P(i64), P(i64)], ctypes.c_int),
         "tlfea_batch_assemble": ([vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "tlfea_batch_assemble_loop": ([vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "tlfea_mesh_set_gather_shape": ([vp, P(GatherShape)], ctypes.c_int),
+        "tlfea_mesh_get_gather_shape": ([vp, P(GatherShape), P(i64)], ctypes.c_int),
+        "tlfea_mesh_autotune": ([vp, vp, vp, dbl, vp, vp, i32, vp, P(GatherShape), P(ctypes.c_float)], ctypes.c_int),
+        "tlfea_batch_set_gather_shape": ([vp, P(GatherShape)], ctypes.c_int),
+        "tlfea_batch_get_gather_shape": ([vp, P(GatherShape), P(i64)], ctypes.c_int),
+        "tlfea_batch_autotune": ([vp, vp, vp, vp, vp, vp, i32, vp, P(GatherShape), P(ctypes.c_float)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

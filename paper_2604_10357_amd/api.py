@@ -172,6 +172,28 @@ class TLMesh:
                 "tlfea_internal_force_vjp")
         return gq, gqd, gp
 
+    def set_gather_shape(self, waves: int, range_tasks: int, range_values: int):
+        sh = N.GatherShape(waves, range_tasks, range_values)
+        N.check(N.lib().tlfea_mesh_set_gather_shape(self._h, ctypes.byref(sh)), "tlfea_mesh_set_gather_shape")
+
+    def gather_shape(self):
+        """(shape dict, number of node ranges)"""
+        sh, n = N.GatherShape(), ctypes.c_int64()
+        N.check(N.lib().tlfea_mesh_get_gather_shape(self._h, ctypes.byref(sh), ctypes.byref(n)),
+                "tlfea_mesh_get_gather_shape")
+        return sh.as_dict(), n.value
+
+    def autotune(self, q, qdot=None, h: float = 1.0, f=None, vals=None, reps: int = 5):
+        """Times the launch-shape grid on tlfea_assemble(q, qdot, h) and keeps the fastest;
+        returns (shape dict, ms per call, f, vals) with f / vals holding its result."""
+        f = torch.empty(self.n_dof, dtype=torch.float64, device=q.device) if f is None else f
+        vals = torch.empty(self.nnz, dtype=torch.float64, device=q.device) if vals is None else vals
+        sh, ms = N.GatherShape(), ctypes.c_float()
+        N.check(N.lib().tlfea_mesh_autotune(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof), float(h),
+                                            _ptr(f, n=self.n_dof), _ptr(vals, n=self.nnz), int(reps), _stream(),
+                                            ctypes.byref(sh), ctypes.byref(ms)), "tlfea_mesh_autotune")
+        return sh.as_dict(), ms.value, f, vals
+
     def runtime_flags(self) -> int:
         fl = ctypes.c_uint32()
         N.check(N.lib().tlfea_get_runtime_flags(self._h, ctypes.byref(fl)), "tlfea_get_runtime_flags")
@@ -213,3 +235,26 @@ class TLBatch:
         N.check(fn(self._h, _ptr(q, n=nd), _ptr(qdot, n=nd), _ptr(h, n=len(self.meshes)), _ptr(f, n=nd),
                    _ptr(vals, n=nz), _stream()), "tlfea_batch_assemble")
         return f, vals
+
+    def set_gather_shape(self, waves: int, range_tasks: int, range_values: int):
+        sh = N.GatherShape(waves, range_tasks, range_values)
+        N.check(N.lib().tlfea_batch_set_gather_shape(self._h, ctypes.byref(sh)), "tlfea_batch_set_gather_shape")
+
+    def gather_shape(self):
+        """(shape dict, number of node ranges over all bodies)"""
+        sh, n = N.GatherShape(), ctypes.c_int64()
+        N.check(N.lib().tlfea_batch_get_gather_shape(self._h, ctypes.byref(sh), ctypes.byref(n)),
+                "tlfea_batch_get_gather_shape")
+        return sh.as_dict(), n.value
+
+    def autotune(self, q, qdot, h, f=None, vals=None, reps: int = 5):
+        """Times the launch-shape grid on the batched launch pair and keeps the fastest;
+        returns (shape dict, ms per call, f, vals) with f / vals holding its result."""
+        nd, nz = self.dof_off[-1], self.nnz_off[-1]
+        f = torch.empty(nd, dtype=torch.float64, device=q.device) if f is None else f
+        vals = torch.empty(nz, dtype=torch.float64, device=q.device) if vals is None else vals
+        sh, ms = N.GatherShape(), ctypes.c_float()
+        N.check(N.lib().tlfea_batch_autotune(self._h, _ptr(q, n=nd), _ptr(qdot, n=nd), _ptr(h, n=len(self.meshes)),
+                                             _ptr(f, n=nd), _ptr(vals, n=nz), int(reps), _stream(),
+                                             ctypes.byref(sh), ctypes.byref(ms)), "tlfea_batch_autotune")
+        return sh.as_dict(), ms.value, f, vals

@@ -30,7 +30,9 @@
 //     stores.  f_int comes out of the same pass from Phat.
 //   Workgroups are remapped so each XCD walks a contiguous range of elements /
 //   nodes, keeping the records a range reads in its own L2.
-#include <atomic>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "kernel_common.h"
 
@@ -626,18 +628,24 @@ __global__ __launch_bounds__(512) void k_gather_batch(BatchArgs b) {
 int grid_of(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 // Dynamic LDS beyond 64 KiB has to be allowed per kernel; the largest size
-// granted so far is remembered per kernel instantiation.
+// granted so far is remembered per kernel (by address: kernels of one
+// signature share a template instantiation here) and device.
 template <typename Kernel>
 int allow_lds(Kernel* kernel, size_t bytes) {
-  static std::atomic<size_t> granted{64 * 1024};
-  if (bytes <= granted.load(std::memory_order_relaxed)) return TLFEA_OK;
+  if (bytes <= 64 * 1024) return TLFEA_OK;
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, size_t> granted;
   int dev = 0, max_bytes = 0;
   TLFEA_HIP_CHECK(hipGetDevice(&dev));
+  const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), dev);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = granted.find(key);
+  if (it != granted.end() && bytes <= it->second) return TLFEA_OK;
   TLFEA_HIP_CHECK(hipDeviceGetAttribute(&max_bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   if (bytes > (size_t)max_bytes) return TLFEA_ERR_UNSUPPORTED;
   TLFEA_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  granted.store(bytes, std::memory_order_relaxed);
+  granted[key] = bytes;
   return TLFEA_OK;
 }
 

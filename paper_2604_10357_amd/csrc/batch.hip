@@ -26,6 +26,8 @@ struct tlfea_batch_s {
   BatchBody* d_bodies = nullptr;
   BatchRange* d_ranges = nullptr;
   int n_ranges = 0;
+  size_t ranges_cap = 0;             // BatchRange entries d_ranges holds
+  tlfea::GatherTuning tune;          // pass-2 launch shape the ranges are cut for
   int64_t n_points = 0, n_blocks = 0;
   size_t lds = 0;
   int inc_cap = 0;
@@ -36,13 +38,63 @@ struct tlfea_batch_s {
   const void* key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
-static void batch_free(tlfea_batch_s* b) {
+static void drop_graph(tlfea_batch_s* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  std::fill(b->key, b->key + 6, nullptr);
+}
+
+static void batch_free(tlfea_batch_s* b) {
+  drop_graph(b);
   (void)hipFree(b->d_bodies);
   (void)hipFree(b->d_ranges);
   (void)hipFree(b->d_stage);
   (void)hipFree(b->d_flags);
   delete b;
+}
+
+// Cut every body's nodes into ranges for launch shape t and upload the
+// concatenated list (the bodies' own cuts are left alone).
+static int batch_set_shape(tlfea_batch_s* b, const tlfea::GatherTuning& t) {
+  if (t.waves < 1 || t.waves > 8 || t.range_tasks < 1 || t.range_values < 1) return TLFEA_ERR_INVALID;
+  std::vector<BatchRange> ranges;
+  int64_t max_vals = 0;
+  int inc_cap = 0;
+  for (size_t i = 0; i < b->meshes.size(); ++i) {
+    const tlfea::Mesh& m = b->meshes[i]->m;
+    const tlfea::RangePlan p = tlfea::plan_ranges(m.h_inc_off, m.h_adj_off, m.mc, t);
+    if (!tlfea::plan_fits(p)) return TLFEA_ERR_UNSUPPORTED;
+    for (size_t r = 0; r + 1 < p.ranges.size(); ++r)
+      ranges.push_back(BatchRange{(int)i, p.ranges[r], p.ranges[r + 1]});
+    max_vals = std::max(max_vals, p.max_values);
+    inc_cap = std::max(inc_cap, (int)((p.max_inc + 15) / 16 * 16));
+  }
+  if (ranges.size() > (size_t)INT32_MAX) return TLFEA_ERR_TOO_LARGE;
+  if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
+  if (ranges.size() > b->ranges_cap || !b->d_ranges) {
+    // queued launches may still read the old list
+    if (b->d_ranges && hipDeviceSynchronize() != hipSuccess) return TLFEA_ERR_HIP;
+    BatchRange* d = nullptr;
+    const size_t cap = ranges.empty() ? 1 : ranges.size();
+    if (hipMalloc(&d, sizeof(BatchRange) * cap) != hipSuccess) {
+      (void)hipGetLastError();
+      return TLFEA_ERR_NOMEM;
+    }
+    (void)hipFree(b->d_ranges);
+    b->d_ranges = d;
+    b->ranges_cap = cap;
+  } else if (hipDeviceSynchronize() != hipSuccess) {
+    return TLFEA_ERR_HIP;
+  }
+  if (!ranges.empty() &&
+      hipMemcpy(b->d_ranges, ranges.data(), sizeof(BatchRange) * ranges.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return TLFEA_ERR_HIP;
+  b->n_ranges = (int)ranges.size();
+  b->lds = sizeof(double) * (size_t)max_vals;
+  b->inc_cap = inc_cap;
+  b->tune = t;
+  drop_graph(b);  // the captured launches hold the old grid and LDS size
+  return TLFEA_OK;
 }
 
 TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, tlfea_batch_t* out) {
@@ -61,14 +113,11 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
   b->gl0 = m0.gl[0];
   b->precision = m0.precision;
   std::vector<BatchBody> bodies(n_bodies);
-  std::vector<BatchRange> ranges;
   b->dof_off.assign(n_bodies + 1, 0);
   b->nnz_off.assign(n_bodies + 1, 0);
-  int64_t max_vals = 0;
   for (int i = 0; i < n_bodies; ++i) {
     const tlfea::Mesh& m = meshes[i]->m;
-    if (m.elem_type != b->elem_type || m.gl[0] != b->gl0 || m.precision != b->precision || m.device != b->device ||
-        m.tune.waves != m0.tune.waves) {
+    if (m.elem_type != b->elem_type || m.gl[0] != b->gl0 || m.precision != b->precision || m.device != b->device) {
       delete b;
       return TLFEA_ERR_INVALID;
     }
@@ -93,9 +142,6 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
     b->nnz_off[i + 1] = b->nnz_off[i] + m.nnz;
     b->n_points += m.n_elem * m.n_qp;
     b->n_blocks += (m.n_elem * m.n_qp + tlfea::kStageThreads - 1) / tlfea::kStageThreads;
-    for (int r = 0; r < m.n_ranges; ++r) ranges.push_back(BatchRange{i, m.h_ranges[r], m.h_ranges[r + 1]});
-    max_vals = std::max(max_vals, m.max_range_values);
-    b->inc_cap = std::max(b->inc_cap, (int)((m.max_range_inc + 15) / 16 * 16));
     // pass 2 addresses a body's records in 16-byte units with 32-bit offsets
     if (m.n_elem * m.n_qp * (int64_t)(tlfea::stage_record_bytes(b->precision) / 16) >= ((int64_t)1 << 32)) {
       delete b;
@@ -103,13 +149,10 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
     }
     b->meshes.push_back(meshes[i]);
   }
-  if (ranges.size() > (size_t)INT32_MAX || b->n_blocks > INT32_MAX) { delete b; return TLFEA_ERR_TOO_LARGE; }
-  b->n_ranges = (int)ranges.size();
-  b->lds = sizeof(double) * (size_t)max_vals;
+  if (b->n_blocks > INT32_MAX) { delete b; return TLFEA_ERR_TOO_LARGE; }
   const size_t stage = (size_t)b->n_points * tlfea::stage_record_bytes(b->precision);
   if (hipSetDevice(b->device) != hipSuccess) { delete b; return TLFEA_ERR_HIP; }
   if (hipMalloc(&b->d_bodies, sizeof(BatchBody) * bodies.size()) != hipSuccess ||
-      hipMalloc(&b->d_ranges, sizeof(BatchRange) * (ranges.empty() ? 1 : ranges.size())) != hipSuccess ||
       hipMalloc(&b->d_stage, stage > 0 ? stage : 1) != hipSuccess ||
       hipMalloc(&b->d_flags, sizeof(uint32_t)) != hipSuccess) {
     (void)hipGetLastError();
@@ -117,11 +160,13 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
     return TLFEA_ERR_NOMEM;
   }
   if (hipMemcpy(b->d_bodies, bodies.data(), sizeof(BatchBody) * bodies.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      (!ranges.empty() &&
-       hipMemcpy(b->d_ranges, ranges.data(), sizeof(BatchRange) * ranges.size(), hipMemcpyHostToDevice) != hipSuccess) ||
       hipMemset(b->d_flags, 0, sizeof(uint32_t)) != hipSuccess) {
     batch_free(b);
     return TLFEA_ERR_HIP;
+  }
+  if (int rc = batch_set_shape(b, m0.tune)) {
+    batch_free(b);
+    return rc;
   }
   *out = b;
   return TLFEA_OK;
@@ -142,14 +187,8 @@ TLFEA_API int tlfea_batch_offsets(tlfea_batch_t batch, int64_t* dof_off, int64_t
   return TLFEA_OK;
 }
 
-static int batch_enqueue(tlfea_batch_t b, const BatchArgs& a, hipStream_t s) {
-  return tlfea::launch_batch(b->elem_type, b->gl0, b->precision, b->meshes[0]->m.tune, a, b->n_ranges, b->lds, s);
-}
-
-TLFEA_API int tlfea_batch_assemble(tlfea_batch_t b, const double* d_q, const double* d_qdot, const double* d_h,
-                                   double* d_f, double* d_vals, void* stream) {
-  if (!b || !d_q || !d_h || !d_f || !d_vals) return TLFEA_ERR_INVALID;
-  if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
+static BatchArgs batch_args(tlfea_batch_t b, const double* d_q, const double* d_qdot, const double* d_h,
+                            double* d_f, double* d_vals) {
   BatchArgs a{};
   a.bodies = b->d_bodies;
   a.ranges = b->d_ranges;
@@ -164,6 +203,18 @@ TLFEA_API int tlfea_batch_assemble(tlfea_batch_t b, const double* d_q, const dou
   a.f = d_f;
   a.vals = d_vals;
   a.flags = b->d_flags;
+  return a;
+}
+
+static int batch_enqueue(tlfea_batch_t b, const BatchArgs& a, hipStream_t s) {
+  return tlfea::launch_batch(b->elem_type, b->gl0, b->precision, b->tune, a, b->n_ranges, b->lds, s);
+}
+
+TLFEA_API int tlfea_batch_assemble(tlfea_batch_t b, const double* d_q, const double* d_qdot, const double* d_h,
+                                   double* d_f, double* d_vals, void* stream) {
+  if (!b || !d_q || !d_h || !d_f || !d_vals) return TLFEA_ERR_INVALID;
+  if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
+  const BatchArgs a = batch_args(b, d_q, d_qdot, d_h, d_f, d_vals);
   auto s = (hipStream_t)stream;
   if (!s) return batch_enqueue(b, a, s);  // the legacy stream cannot be captured
   const void* key[6] = {d_q, d_qdot, d_h, d_f, d_vals, stream};
@@ -208,5 +259,44 @@ TLFEA_API int tlfea_batch_assemble_loop(tlfea_batch_t b, const double* d_q, cons
                                1.0, d_f + b->dof_off[i], d_vals + b->nnz_off[i], stream);
     if (rc) return rc;
   }
+  return TLFEA_OK;
+}
+
+TLFEA_API int tlfea_batch_set_gather_shape(tlfea_batch_t b, const tlfea_gather_shape* shape) {
+  if (!b || !shape) return TLFEA_ERR_INVALID;
+  return batch_set_shape(b, tlfea::GatherTuning{shape->waves, shape->range_tasks, shape->range_values});
+}
+
+TLFEA_API int tlfea_batch_get_gather_shape(tlfea_batch_t b, tlfea_gather_shape* shape, int64_t* n_ranges) {
+  if (!b || (!shape && !n_ranges)) return TLFEA_ERR_INVALID;
+  if (shape) {
+    shape->waves = b->tune.waves;
+    shape->range_tasks = b->tune.range_tasks;
+    shape->range_values = b->tune.range_values;
+  }
+  if (n_ranges) *n_ranges = b->n_ranges;
+  return TLFEA_OK;
+}
+
+TLFEA_API int tlfea_batch_autotune(tlfea_batch_t b, const double* d_q, const double* d_qdot, const double* d_h,
+                                   double* d_f, double* d_vals, int32_t reps, void* stream,
+                                   tlfea_gather_shape* chosen, float* ms_per_call) {
+  if (!b || !d_q || !d_h || !d_f || !d_vals) return TLFEA_ERR_INVALID;
+  if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
+  const auto s = (hipStream_t)stream;
+  const tlfea::GatherTuning current = b->tune;
+  tlfea::GatherTuning best = current;
+  float ms = 0.0f;
+  // the launch pair itself, uncaptured: shapes change between the timings
+  const int rc = tlfea::autotune_shape(
+      current, [&](const tlfea::GatherTuning& t) { return batch_set_shape(b, t); },
+      [&]() { return batch_enqueue(b, batch_args(b, d_q, d_qdot, d_h, d_f, d_vals), s); }, reps, s, best, ms);
+  if (rc) return rc;
+  if (chosen) {
+    chosen->waves = best.waves;
+    chosen->range_tasks = best.range_tasks;
+    chosen->range_values = best.range_values;
+  }
+  if (ms_per_call) *ms_per_call = ms;
   return TLFEA_OK;
 }

@@ -540,3 +540,47 @@ TLFEA_API int tlfea_get_runtime_flags(tlfea_mesh_t mesh, uint32_t* flags) {
   TLFEA_HIP_CHECK(hipMemset(m.d_flags, 0, sizeof(uint32_t)));
   return TLFEA_OK;
 }
+
+static tlfea::GatherTuning shape_in(const tlfea_gather_shape& s) {
+  return tlfea::GatherTuning{s.waves, s.range_tasks, s.range_values};
+}
+
+static void shape_out(const tlfea::GatherTuning& t, tlfea_gather_shape* s) {
+  if (!s) return;
+  s->waves = t.waves;
+  s->range_tasks = t.range_tasks;
+  s->range_values = t.range_values;
+}
+
+TLFEA_API int tlfea_mesh_set_gather_shape(tlfea_mesh_t mesh, const tlfea_gather_shape* shape) {
+  if (!mesh || !shape) return TLFEA_ERR_INVALID;
+  return tlfea::set_gather_shape(mesh->m, shape_in(*shape));
+}
+
+TLFEA_API int tlfea_mesh_get_gather_shape(tlfea_mesh_t mesh, tlfea_gather_shape* shape, int64_t* n_ranges) {
+  if (!mesh || (!shape && !n_ranges)) return TLFEA_ERR_INVALID;
+  if (!mesh->m.has_pattern) return TLFEA_ERR_NO_PATTERN;
+  shape_out(mesh->m.tune, shape);
+  if (n_ranges) *n_ranges = mesh->m.n_ranges;
+  return TLFEA_OK;
+}
+
+TLFEA_API int tlfea_mesh_autotune(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double h,
+                                  double* d_f, double* d_vals, int32_t reps, void* stream,
+                                  tlfea_gather_shape* chosen, float* ms_per_call) {
+  int rc = tlfea::check_call(mesh, d_q, true);
+  if (rc) return rc;
+  if (!d_f || !d_vals || !std::isfinite(h)) return TLFEA_ERR_INVALID;
+  Mesh& m = mesh->m;
+  const tlfea::GatherTuning current = m.tune;
+  tlfea::GatherTuning best = current;
+  float ms = 0.0f;
+  rc = tlfea::autotune_shape(
+      current, [&](const tlfea::GatherTuning& t) { return tlfea::set_gather_shape(m, t); },
+      [&]() { return run_assembly(mesh, d_q, d_qdot, h, 1.0, d_f, d_vals, stream); }, reps,
+      (hipStream_t)stream, best, ms);
+  if (rc) return rc;
+  shape_out(best, chosen);
+  if (ms_per_call) *ms_per_call = ms;
+  return TLFEA_OK;
+}

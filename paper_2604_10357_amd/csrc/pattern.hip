@@ -314,42 +314,15 @@ int build_pattern(Mesh& m) {
   hipError_t e4 = hipGetLastError();
   hipError_t e5 = hipMemcpy(h_inc_off.data(), d_inc_off, sizeof(int32_t) * (nn + 1), hipMemcpyDeviceToHost);
   hipError_t e6 = hipMemcpy(h_adj_off.data(), d_adj_off, sizeof(int32_t) * (nn + 1), hipMemcpyDeviceToHost);
-  // greedy partition of the nodes into ranges of bounded tasks and LDS values
   const GatherTuning tune = gather_tuning();
-  std::vector<int32_t> ranges{0};
-  int64_t max_vals = 0, max_rows = 0, max_inc = 0;
-  {
-    int64_t tasks = 0, vals = 0, rows = 0, nodes = 0, incs = 0;
-    for (int64_t I = 0; I < nn; ++I) {
-      const int64_t tI = 9LL * mc * (h_inc_off[I + 1] - h_inc_off[I]);
-      const int64_t vI = 9LL * mc * mc * (h_adj_off[I + 1] - h_adj_off[I]) + 3LL * mc;
-      if (nodes > 0 && (tasks + tI > tune.range_tasks || vals + vI > tune.range_values || nodes >= kMaxRangeNodes)) {
-        ranges.push_back((int32_t)I);
-        max_vals = std::max(max_vals, vals);
-        max_rows = std::max(max_rows, rows);
-        max_inc = std::max(max_inc, incs);
-        tasks = vals = rows = nodes = incs = 0;
-      }
-      incs += h_inc_off[I + 1] - h_inc_off[I];
-      tasks += tI;
-      vals += vI;
-      rows += 3LL * mc;
-      ++nodes;
-    }
-    if (nodes > 0) {
-      ranges.push_back((int32_t)nn);
-      max_vals = std::max(max_vals, vals);
-      max_rows = std::max(max_rows, rows);
-      max_inc = std::max(max_inc, incs);
-    }
-  }
+  RangePlan plan = plan_ranges(h_inc_off, h_adj_off, mc, tune);
   int32_t* d_ranges = nullptr;
-  hipError_t e7 = hipMalloc(&d_ranges, sizeof(int32_t) * ranges.size());
-  hipError_t e8 = e7 == hipSuccess ? hipMemcpy(d_ranges, ranges.data(), sizeof(int32_t) * ranges.size(),
+  hipError_t e7 = hipMalloc(&d_ranges, sizeof(int32_t) * plan.ranges.size());
+  hipError_t e8 = e7 == hipSuccess ? hipMemcpy(d_ranges, plan.ranges.data(), sizeof(int32_t) * plan.ranges.size(),
                                                hipMemcpyHostToDevice)
                                    : e7;
   // a range's LDS segment must fit next to the staging buffers (checked again at launch)
-  const bool too_big = max_vals * (int64_t)sizeof(double) > 96 * 1024;
+  const bool too_big = !plan_fits(plan);
   if (e4 != hipSuccess || e5 != hipSuccess || e6 != hipSuccess || e8 != hipSuccess || too_big) {
     (void)hipFree(d_row_off); (void)hipFree(d_cols); (void)hipFree(d_rank);
     (void)hipFree(d_adj_off); (void)hipFree(d_adj); (void)hipFree(d_ranges);
@@ -369,12 +342,14 @@ int build_pattern(Mesh& m) {
   m.d_inc_off = d_inc_off;
   m.d_inc = d_inc;
   m.d_ranges = d_ranges;
-  m.h_ranges = std::move(ranges);
+  m.h_ranges = std::move(plan.ranges);
   m.n_ranges = (int)m.h_ranges.size() - 1;
-  m.max_range_values = max_vals;
-  m.max_range_rows = max_rows;
-  m.max_range_inc = max_inc;
+  m.max_range_values = plan.max_values;
+  m.max_range_rows = plan.max_rows;
+  m.max_range_inc = plan.max_inc;
   m.tune = tune;
+  m.h_inc_off = std::move(h_inc_off);
+  m.h_adj_off = std::move(h_adj_off);
   m.nnz = nnz;
   m.has_pattern = true;
   return TLFEA_OK;
@@ -393,6 +368,74 @@ GatherTuning gather_tuning() {
   t.range_tasks = env_int("TLFEA_RANGE_TASKS", t.range_tasks, 1, 1 << 20);
   t.range_values = env_int("TLFEA_RANGE_VALUES", t.range_values, 1, 12 * 1024);
   return t;
+}
+
+RangePlan plan_ranges(const std::vector<int32_t>& inc_off, const std::vector<int32_t>& adj_off, int mc,
+                      const GatherTuning& t) {
+  RangePlan p;
+  const int64_t nn = (int64_t)inc_off.size() - 1;
+  int64_t tasks = 0, vals = 0, rows = 0, nodes = 0, incs = 0;
+  auto close = [&](int64_t end) {
+    p.ranges.push_back((int32_t)end);
+    p.max_values = std::max(p.max_values, vals);
+    p.max_rows = std::max(p.max_rows, rows);
+    p.max_inc = std::max(p.max_inc, incs);
+    tasks = vals = rows = nodes = incs = 0;
+  };
+  for (int64_t I = 0; I < nn; ++I) {
+    const int64_t nI = inc_off[I + 1] - inc_off[I];
+    const int64_t tI = 9LL * mc * nI;                                     // tasks of the node
+    const int64_t vI = 9LL * mc * mc * (adj_off[I + 1] - adj_off[I]) + 3LL * mc;  // its CSR values + force rows
+    if (nodes > 0 && (tasks + tI > t.range_tasks || vals + vI > t.range_values || nodes >= kMaxRangeNodes)) close(I);
+    incs += nI;
+    tasks += tI;
+    vals += vI;
+    rows += 3LL * mc;
+    ++nodes;
+  }
+  if (nodes > 0) close(nn);
+  return p;
+}
+
+std::vector<GatherTuning> gather_candidates() {
+  std::vector<GatherTuning> c;
+  for (int w : {2, 4, 8})
+    for (int t : {384, 768, 1536})
+      for (int v : {2048, 4096, 8192}) c.push_back(GatherTuning{w, t, v});
+  return c;
+}
+
+bool plan_fits(const RangePlan& p) { return p.max_values * (int64_t)sizeof(double) <= kMaxSegmentBytes; }
+
+int set_gather_shape(Mesh& m, const GatherTuning& t) {
+  if (!m.has_pattern) return TLFEA_ERR_NO_PATTERN;
+  if (t.waves < 1 || t.waves > 8 || t.range_tasks < 1 || t.range_values < 1) return TLFEA_ERR_INVALID;
+  RangePlan p = plan_ranges(m.h_inc_off, m.h_adj_off, m.mc, t);
+  if (!plan_fits(p)) return TLFEA_ERR_UNSUPPORTED;
+  if (hipSetDevice(m.device) != hipSuccess) return TLFEA_ERR_HIP;
+  int32_t* d = nullptr;
+  if (hipMalloc(&d, sizeof(int32_t) * p.ranges.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    return TLFEA_ERR_NOMEM;
+  }
+  if (hipMemcpy(d, p.ranges.data(), sizeof(int32_t) * p.ranges.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return TLFEA_ERR_HIP;
+  }
+  // the old ranges may still be read by queued work on the mesh's last stream
+  if (m.d_ranges && hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(d);
+    return TLFEA_ERR_HIP;
+  }
+  (void)hipFree(m.d_ranges);
+  m.d_ranges = d;
+  m.h_ranges = std::move(p.ranges);
+  m.n_ranges = (int)m.h_ranges.size() - 1;
+  m.max_range_values = p.max_values;
+  m.max_range_rows = p.max_rows;
+  m.max_range_inc = p.max_inc;
+  m.tune = t;
+  return TLFEA_OK;
 }
 
 int export_slot_map(const Mesh& m, int64_t e0, int64_t ne, int32_t* d_out, hipStream_t s) {

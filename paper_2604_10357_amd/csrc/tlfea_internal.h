@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <vector>
 
@@ -40,6 +41,91 @@ struct GatherTuning {
 // defaults, overridden by TLFEA_GATHER_WAVES / TLFEA_RANGE_TASKS /
 // TLFEA_RANGE_VALUES when set (tuning sweeps)
 GatherTuning gather_tuning();
+// a range's LDS segment (CSR values + force rows) must stay below this
+constexpr int64_t kMaxSegmentBytes = 96 * 1024;
+
+// Greedy cut of the pattern nodes 0 .. n-1, in order, into ranges of at most
+// t.range_tasks tasks and t.range_values LDS doubles (a single node may exceed
+// both; at most kMaxRangeNodes nodes).  inc_off / adj_off: node -> incident
+// elements / adjacent nodes, n + 1 prefix offsets each.
+struct RangePlan {
+  std::vector<int32_t> ranges{0};  // n_ranges + 1 node boundaries
+  int64_t max_values = 0, max_rows = 0, max_inc = 0;
+};
+RangePlan plan_ranges(const std::vector<int32_t>& inc_off, const std::vector<int32_t>& adj_off, int mc,
+                      const GatherTuning& t);
+bool plan_fits(const RangePlan& p);  // every segment below kMaxSegmentBytes
+
+// Launch shapes the autotuners time: waves {2, 4, 8} x range_tasks {384, 768,
+// 1536} x range_values {2048, 4096, 8192}.
+std::vector<GatherTuning> gather_candidates();
+
+// Autotuning loop shared by meshes and batches.  Every candidate that apply(t)
+// accepts (TLFEA_ERR_UNSUPPORTED: skipped) is run() once to warm up and then
+// `reps` times between two events on stream s.  The shape in use is timed
+// first (after three warm-up calls) and again last, and keeps the lower of its
+// two times, so that its place in the sweep does not count against it.  The
+// fastest candidate replaces it only if it is at least kTuneMargin faster
+// (shapes within a few percent trade places from run to run); the chosen shape
+// is applied again and run() once more, so the outputs hold its result.  On an
+// error the shape `current` is restored.  Synchronises the stream.
+constexpr float kTuneMargin = 0.05f;
+template <class Apply, class Run>
+int autotune_shape(const GatherTuning& current, Apply&& apply, Run&& run, int reps, hipStream_t s,
+                   GatherTuning& best, float& best_ms) {
+  if (reps < 1 || reps > 1000) return TLFEA_ERR_INVALID;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    (void)hipGetLastError();
+    return TLFEA_ERR_HIP;
+  }
+  auto same = [](const GatherTuning& a, const GatherTuning& b) {
+    return a.waves == b.waves && a.range_tasks == b.range_tasks && a.range_values == b.range_values;
+  };
+  std::vector<GatherTuning> cand{current};
+  for (const GatherTuning& t : gather_candidates())
+    if (!same(t, current)) cand.push_back(t);
+  cand.push_back(current);
+  best_ms = -1.0f;
+  float current_ms = -1.0f;
+  int rc = TLFEA_OK;
+  for (size_t c = 0; c < cand.size(); ++c) {
+    const GatherTuning& t = cand[c];
+    rc = apply(t);
+    if (rc == TLFEA_ERR_UNSUPPORTED) continue;
+    for (int i = 0; !rc && i < (c == 0 ? 3 : 1); ++i) rc = run();
+    if (rc == TLFEA_ERR_UNSUPPORTED) continue;  // more LDS than the device gives a workgroup
+    for (int i = 0; !rc && i < reps; ++i) {
+      if (i == 0 && hipEventRecord(e0, s) != hipSuccess) rc = TLFEA_ERR_HIP;
+      if (!rc) rc = run();
+    }
+    float ms = 0.0f;
+    if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = TLFEA_ERR_HIP;
+    if (rc) break;
+    ms /= (float)reps;
+    if (same(t, current)) current_ms = current_ms < 0.0f ? ms : std::min(current_ms, ms);
+    if (best_ms < 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  if (!rc && current_ms >= 0.0f && best_ms > (1.0f - kTuneMargin) * current_ms) {
+    best = current;  // not worth a change
+    best_ms = current_ms;
+  }
+  if (!rc && best_ms < 0.0f) rc = TLFEA_ERR_UNSUPPORTED;  // no candidate fits
+  if (!rc) {
+    rc = apply(best);
+    if (!rc) rc = run();
+  }
+  if (rc) (void)apply(current);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
 
 // Per-mesh state.  All d_* members are device allocations owned by the mesh.
 struct Mesh {
@@ -76,6 +162,8 @@ struct Mesh {
   int64_t max_range_rows = 0;     // largest number of force rows of a range
   int64_t max_range_inc = 0;      // largest number of incidences of a range
   GatherTuning tune;              // launch shape the ranges were cut for
+  std::vector<int32_t> h_inc_off; // host copies of inc_off / adj_off (range cuts)
+  std::vector<int32_t> h_adj_off;
   void* d_stage = nullptr;        // pass-1 records
   size_t stage_cap = 0;
   int staged = 0;                 // what the last pass 1 left: 0 none, 1 force records, 2 force + tangent
@@ -178,6 +266,9 @@ int launch_nodes(const Mesh& m, double* f, double* vals, bool accumulate, hipStr
 
 // pattern builder (pattern.hip)
 int build_pattern(Mesh& m);
+// re-cut the mesh's node ranges for launch shape t (needs the pattern);
+// TLFEA_ERR_UNSUPPORTED if a range would not fit, leaving the mesh unchanged
+int set_gather_shape(Mesh& m, const GatherTuning& t);
 int export_slot_map(const Mesh& m, int64_t e0, int64_t ne, int32_t* d_out, hipStream_t s);
 
 // geometry precompute (mesh.hip)

@@ -2,9 +2,12 @@
 
 Run under ``rocprofv3 --pmc``, once per counter (FETCH_SIZE, then WRITE_SIZE):
 
-    rocprofv3 --pmc FETCH_SIZE -d <dir>/fetch -o pmc -- python3 -m paper_2604_10357_amd.pmc run
-    rocprofv3 --pmc WRITE_SIZE -d <dir>/write -o pmc -- python3 -m paper_2604_10357_amd.pmc run
-    python3 -m paper_2604_10357_amd.pmc report <dir> <out.json>
+    rocprofv3 --pmc FETCH_SIZE -d <dir>/fetch -o pmc -- python3 -m paper_2604_10357_amd.pmc run [W T V]
+    rocprofv3 --pmc WRITE_SIZE -d <dir>/write -o pmc -- python3 -m paper_2604_10357_amd.pmc run [W T V]
+    python3 -m paper_2604_10357_amd.pmc report <dir> <out.json> [W T V]
+
+W T V is the pass-2 launch shape (waves, range_tasks, range_values) the
+assemblies use; without it, the library's default.
 
 The workload assembles the 480,000-element T10 beam (Mooney-Rivlin +
 Kelvin-Voigt, mixed precision) three times and copies a 1 GiB device buffer
@@ -39,7 +42,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def run() -> None:
+DEFAULT_SHAPE = {"waves": 4, "range_tasks": 768, "range_values": 4096}
+
+
+def _shape(args) -> dict:
+    if not args:
+        return dict(DEFAULT_SHAPE)
+    w, t, v = (int(x) for x in args)
+    return {"waves": w, "range_tasks": t, "range_values": v}
+
+
+def run(shape: dict) -> None:
     import torch
 
     from . import workloads as W
@@ -48,6 +61,7 @@ def run() -> None:
     wl = W.config5()
     m = TLMesh(wl.mesh, wl.material, "mixed")
     m.build_pattern()
+    m.set_gather_shape(shape["waves"], shape["range_tasks"], shape["range_values"])
     q = torch.from_numpy(wl.q).cuda()
     qd = torch.from_numpy(wl.qdot).cuda()
     f = torch.empty(m.n_dof, dtype=torch.float64, device="cuda")
@@ -77,9 +91,9 @@ def _per_kernel(db_dir: str, counter: str) -> dict:
     return out
 
 
-def report(base: str, out_json: str) -> dict:
-    res = {"workload": "t10_beam_200x20x20_mr_kv mixed", "kernel_source_sha256": kernel_source_hash(),
-           "copy_bytes": COPY_BYTES, "kernels": {}}
+def report(base: str, out_json: str, shape: dict) -> dict:
+    res = {"workload": "t10_beam_200x20x20_mr_kv mixed", "gather_shape": shape,
+           "kernel_source_sha256": kernel_source_hash(), "copy_bytes": COPY_BYTES, "kernels": {}}
     for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
         per = _per_kernel(os.path.join(base, sub), counter)
         copy = max(per.get("__amd_rocclr_copyBuffer", [0.0]))
@@ -102,10 +116,10 @@ def report(base: str, out_json: str) -> dict:
 
 
 if __name__ == "__main__":
-    if len(sys.argv) >= 2 and sys.argv[1] == "run":
-        run()
-    elif len(sys.argv) == 4 and sys.argv[1] == "report":
-        print(json.dumps(report(sys.argv[2], sys.argv[3]), indent=1))
+    if len(sys.argv) in (2, 5) and sys.argv[1] == "run":
+        run(_shape(sys.argv[2:]))
+    elif len(sys.argv) in (4, 7) and sys.argv[1] == "report":
+        print(json.dumps(report(sys.argv[2], sys.argv[3], _shape(sys.argv[4:])), indent=1))
     else:
         print(__doc__)
         sys.exit(2)

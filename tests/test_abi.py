@@ -62,6 +62,20 @@ def test_descriptor_layout_matches_header(native, tmp_path):
     assert got == want
 
 
+def test_gather_shape_layout_matches_header(native, tmp_path):
+    src = tmp_path / "shape.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "tlfea.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu\\n\", sizeof(tlfea_gather_shape),"
+        " offsetof(tlfea_gather_shape, waves), offsetof(tlfea_gather_shape, range_tasks),"
+        " offsetof(tlfea_gather_shape, range_values));return 0;}\n")
+    exe = tmp_path / "shape"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    G = native.GatherShape
+    assert got == [ctypes.sizeof(G), G.waves.offset, G.range_tasks.offset, G.range_values.offset]
+
+
 def test_status_strings_and_version(native):
     L = native.lib()
     assert L.tlfea_version() >= 100
@@ -134,3 +148,10 @@ def test_argument_validation_needs_no_gpu(native):
     assert L.tlfea_mesh_info(None, None, None, None, None, None) == -1
     assert L.tlfea_batch_create(None, 0, ctypes.byref(h)) == -1
     assert L.tlfea_batch_destroy(None) == 0
+    sh = native.GatherShape(4, 768, 4096)
+    assert L.tlfea_mesh_set_gather_shape(None, ctypes.byref(sh)) == -1
+    assert L.tlfea_mesh_get_gather_shape(None, ctypes.byref(sh), None) == -1
+    assert L.tlfea_mesh_autotune(None, None, None, 1.0, None, None, 5, None, None, None) == -1
+    assert L.tlfea_batch_set_gather_shape(None, ctypes.byref(sh)) == -1
+    assert L.tlfea_batch_get_gather_shape(None, ctypes.byref(sh), None) == -1
+    assert L.tlfea_batch_autotune(None, None, None, None, None, None, 5, None, None, None) == -1

@@ -69,8 +69,7 @@ def measured_traffic(precision, shape):
     if rep.get("gather_shape", pmc.DEFAULT_SHAPE) != shape:
         return None
     ks = rep["kernels"]
-    names = [k for k in ks if k.startswith("k_stage_tile<RuleT10, float>") or
-             k.startswith("k_gather<RuleT10, float, true, true, false>")]
+    names = [k for k in ks if k.startswith("k_elem_rows<RuleT10>") or k.startswith("k_gather_rows<true, true, false>")]
     if len(names) != 2:
         return None
     return sum(ks[k]["hbm_bytes"] for k in names)
@@ -220,6 +219,8 @@ def bench_mesh(args, torch, wl, wname):
     achieved = B / (ms * 1e-3) / 1e9
     traffic = measured_traffic(args.precision, tuning["gather_shape"]) if wname == "t10_beam" else None
     kname = "T10" if wl.mesh.elem_type == 1 else "ANCF3443"
+    # T10 with the tangent in mixed precision takes the element-row kernels
+    rows_path = wl.mesh.elem_type == 1 and args.precision == "mixed" and os.environ.get("TLFEA_ELEMENT_ROWS") != "0"
     mat = "mooney_rivlin" if wl.material.kind == 2 else "svk"
     if wl.material.kv_eta or wl.material.kv_lambda:
         mat += "+kelvin_voigt"
@@ -241,13 +242,16 @@ def bench_mesh(args, torch, wl, wname):
         "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_stage_tile + k_gather ({kname}, f + K)", "kernel_ms": ms,
+                     "kernel": (f"k_elem_rows + k_gather_rows ({kname}, f + K)" if rows_path else
+                                f"k_stage_tile + k_gather ({kname}, f + K)"), "kernel_ms": ms,
                      "pass1_stage_ms": ms1, "pass2_gather_ms": ms2, "algorithmic_bytes": B},
     }
     ro, cols = mesh.csr_pattern(on_device=False)
     ro, cols = ro.numpy(), cols.numpy()
     if not args.no_fp64 and args.precision == "mixed":
         mesh.set_precision("fp64")
+        # the FP64 kernels get a launch shape of their own
+        tuning64 = autotune(args, mesh, lambda: mesh.autotune(q, qd, h, f, vals, reps=5))
         for _ in range(args.warmup):
             step()
         ms64 = time_calls(step, args.steps, torch)
@@ -257,7 +261,8 @@ def bench_mesh(args, torch, wl, wname):
         torch.cuda.synchronize()
         f64, v64 = f.cpu().numpy(), vals.cpu().numpy()
         mesh.set_precision(args.precision)
-        out["fp64"] = {"value": n_el / (ms64 * 1e-3), "ms_per_step": ms64, "pass1_stage_ms": ms64_1,
+        mesh.set_gather_shape(*[tuning["gather_shape"][k] for k in ("waves", "range_tasks", "range_values")])
+        out["fp64"] = {"value": n_el / (ms64 * 1e-3), "ms_per_step": ms64, "tuning": tuning64, "pass1_stage_ms": ms64_1,
                        "pass2_gather_ms": ms64_2, "achieved_GBs": B / (ms64 * 1e-3) / 1e9,
                        "speedup_mixed_over_fp64": ms64 / ms}
         # mixed against the FP64 GPU result over the whole output

@@ -30,6 +30,7 @@
 //     stores.  f_int comes out of the same pass from Phat.
 //   Workgroups are remapped so each XCD walks a contiguous range of elements /
 //   nodes, keeping the records a range reads in its own L2.
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -112,6 +113,67 @@ __device__ __forceinline__ R record_value(const HatOut<R>& h) {
   }
 }
 
+// Nodal values of a workgroup's elements in LDS: 6 doubles per (element,
+// coefficient), u = q - X then qdot (zero without qdot), for elements
+// e_lo .. e_lo + ne - 1.
+template <class Rule>
+__device__ __forceinline__ void gather_nodal(const AsmArgs& a, int64_t e_lo, int ne, double* nod) {
+  constexpr int NEN = Rule::NEN, NPN = Rule::NPN;
+  for (int idx = threadIdx.x; idx < ne * NEN; idx += blockDim.x) {
+    const int le = idx / NEN, al = idx - le * NEN;
+    const int64_t e = e_lo + le;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (e < a.n_elem) {
+      const int64_t c = coef_of<Rule>(a.conn + e * NPN, al);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) v[i] = a.q[3 * c + i] - a.X[3 * c + i];
+      if (a.qdot) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) v[3 + i] = a.qdot[3 * c + i];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 6; ++t) nod[6 * idx + t] = v[t];
+  }
+}
+
+// Displacement and velocity gradients at point q of element e from its nodal
+// values in LDS (ne: 6 doubles per coefficient): Hd = sum_a u_a (x) g_a,
+// Fd = sum_a qdot_a (x) g_a, with g_a = J0^-T dN_a (Sec. 4.3, Eq. F_assembly).
+template <class Rule>
+__device__ __forceinline__ void tile_kinematics(const AsmArgs& a, const double* ne, int64_t e, int q,
+                                                double (&Jinv)[9], double& det, double (&Hd)[9], double (&Fd)[9]) {
+  constexpr int NEN = Rule::NEN;
+  double sc[4];
+  load_geometry<Rule>(a, e, q, Jinv, det);
+  element_scales<Rule>(a, e, sc);
+  double Du[9], Dv[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) Du[t] = Dv[t] = 0.0;
+#pragma unroll
+  for (int al = 0; al < NEN; ++al) {
+    const double s = sc[al % 4];
+    const double w0 = Rule::dN_rt(q, al, 0) * s, w1 = Rule::dN_rt(q, al, 1) * s, w2 = Rule::dN_rt(q, al, 2) * s;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double u = ne[6 * al + i], v = ne[6 * al + 3 + i];
+      Du[3 * i] += u * w0;
+      Du[3 * i + 1] += u * w1;
+      Du[3 * i + 2] += u * w2;
+      Dv[3 * i] += v * w0;
+      Dv[3 * i + 1] += v * w1;
+      Dv[3 * i + 2] += v * w2;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      Hd[3 * i + J] = Du[3 * i] * Jinv[J] + Du[3 * i + 1] * Jinv[3 + J] + Du[3 * i + 2] * Jinv[6 + J];
+      Fd[3 * i + J] = Dv[3 * i] * Jinv[J] + Dv[3 * i + 1] * Jinv[3 + J] + Dv[3 * i + 2] * Jinv[6 + J];
+    }
+}
+
 // Pass 1 with the tangent, one workgroup per 256 consecutive (element, point)
 // indices.  The nodal values of the workgroup's elements (u = q - X and qdot
 // per coefficient) are gathered into LDS once instead of once per point, and
@@ -143,58 +205,15 @@ __device__ __forceinline__ void stage_tile(const AsmArgs& a, R* stage, int64_t b
   const bool act = p < npts;
   // 1. nodal values of the elements the block's points belong to
   double* nod = reinterpret_cast<double*>(smem);
-  for (int idx = tid; idx < EB * NEN; idx += kStageThreads) {
-    const int le = idx / NEN, al = idx - le * NEN;
-    const int64_t e = e_lo + le;
-    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (e < a.n_elem) {
-      const int64_t c = coef_of<Rule>(a.conn + e * NPN, al);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) v[i] = a.q[3 * c + i] - a.X[3 * c + i];
-      if (a.qdot) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) v[3 + i] = a.qdot[3 * c + i];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 6; ++t) nod[6 * idx + t] = v[t];
-  }
+  gather_nodal<Rule>(a, e_lo, EB, nod);
   __syncthreads();
   // 2. kinematics at the lane's point (lanes past the end evaluate the last
   //    point and store nothing)
   const int64_t pc = act ? p : npts - 1;
   const int64_t e = pc / NQ;
   const int q = (int)(pc - e * NQ);
-  const double* ne = nod + 6 * NEN * (int)(e - e_lo);
-  double Jinv[9], det, sc[4];
-  load_geometry<Rule>(a, e, q, Jinv, det);
-  element_scales<Rule>(a, e, sc);
-  double Du[9], Dv[9];
-#pragma unroll
-  for (int t = 0; t < 9; ++t) Du[t] = Dv[t] = 0.0;
-#pragma unroll
-  for (int al = 0; al < NEN; ++al) {
-    const double s = sc[al % 4];
-    const double w0 = Rule::dN_rt(q, al, 0) * s, w1 = Rule::dN_rt(q, al, 1) * s, w2 = Rule::dN_rt(q, al, 2) * s;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double u = ne[6 * al + i], v = ne[6 * al + 3 + i];
-      Du[3 * i] += u * w0;
-      Du[3 * i + 1] += u * w1;
-      Du[3 * i + 2] += u * w2;
-      Dv[3 * i] += v * w0;
-      Dv[3 * i + 1] += v * w1;
-      Dv[3 * i + 2] += v * w2;
-    }
-  }
-  double Hd[9], Fd[9];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int J = 0; J < 3; ++J) {
-      Hd[3 * i + J] = Du[3 * i] * Jinv[J] + Du[3 * i + 1] * Jinv[3 + J] + Du[3 * i + 2] * Jinv[6 + J];
-      Fd[3 * i + J] = Dv[3 * i] * Jinv[J] + Dv[3 * i + 1] * Jinv[3 + J] + Dv[3 * i + 2] * Jinv[6 + J];
-    }
+  double Jinv[9], det, Hd[9], Fd[9];
+  tile_kinematics<Rule>(a, nod + 6 * NEN * (int)(e - e_lo), e, q, Jinv, det, Hd, Fd);
   __syncthreads();  // the nodal values are consumed: the LDS becomes the transpose buffers
   PointOut<R> o;
   const unsigned fl = point_update<R, true>(a.mp, Hd, Fd, det * Rule::w_rt(q), a.alpha, a.beta, o);
@@ -623,6 +642,248 @@ __global__ __launch_bounds__(512) void k_gather_batch(BatchArgs b) {
 }
 
 // ---------------------------------------------------------------------------
+// element rows (T10, float32, with the tangent)
+// ---------------------------------------------------------------------------
+// Pass 1 reduces over the points itself.  A workgroup computes the records of
+// kRowElems whole elements into LDS (a lane per point, as above), then a lane
+// per task (element, node a, row i, component k) contracts the element's five
+// records exactly as the gather does, giving the ten entries
+// K_e[3a+i][3b+k], b = 0..9, summed over the points in float32 (Sec. 4.4.2,
+// Eq. tangent_block), and its part P_ik dN_a,k of f_a,i (Eq. fint_local).
+// Each (element, node) row block goes to the node's place in the node-sorted
+// incidence list, so that pass 2 reads the blocks of a node range as one
+// contiguous run, each block once, instead of re-reading per-point records
+// for every range that shares an element.
+constexpr int kRowBlk = 96;       // block: K entry (i, k, b) at 10 (3 i + k) + b, f_i at 90 + i
+constexpr int kRowElems = 25;     // elements per pass-1 workgroup
+constexpr int kRowThreads = 128;  // 125 point lanes
+constexpr int kRecL = 92;         // LDS record stride in values (a 16-byte multiple)
+constexpr int kRowStage = 7;      // incidences a wave contracts at a time (63 of its lanes)
+
+template <class Rule>
+__device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* __restrict__ incpos,
+                                               float* __restrict__ rows, int64_t blk) {
+  static_assert(Rule::MC == 1 && Rule::NEN == 10, "element rows are built for T10");
+  constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN;
+  static_assert(kRowElems * NQ <= kRowThreads, "a lane per point");
+  static_assert(kRowThreads % 64 == 0 && 9 * kRowStage <= 64, "a wave stages whole incidences");
+  __shared__ __align__(16) float rec[kRowElems * NQ * kRecL];
+  __shared__ __align__(16) float dn[NEN * 16];   // parent gradients of every node at every point
+  __shared__ int32_t pos[kRowElems * NEN];         // incidence position of every (element, node)
+  __shared__ __align__(16) float stage_buf[(kRowThreads / 64) * kRowStage * kRowBlk];  // per-wave row blocks
+  static_assert(kRowElems * NEN * 6 * sizeof(double) <= sizeof(rec), "nodal values fit the record area");
+  const int tid = threadIdx.x;
+  const int64_t e0 = blk * kRowElems;
+  const int ne = (int)(a.n_elem - e0 < kRowElems ? a.n_elem - e0 : kRowElems);
+  // 1. nodal values, the tables of the tasks, then each point's kinematics
+  double* nod = reinterpret_cast<double*>(rec);
+  gather_nodal<Rule>(a, e0, ne, nod);
+  for (int idx = tid; idx < ne * NEN; idx += kRowThreads) pos[idx] = incpos[e0 * NPN + idx];
+  for (int idx = tid; idx < NEN * 16; idx += kRowThreads) dn[idx] = Rule::template rows<float>(idx / 16)[idx % 16];
+  __syncthreads();
+  const bool act = tid < ne * NQ;
+  const int pl = act ? tid : 0;  // idle lanes evaluate point 0 and store nothing
+  const int el = pl / NQ, q = pl - el * NQ;
+  double Jinv[9], det, Hd[9], Fd[9];
+  tile_kinematics<Rule>(a, nod + 6 * NEN * el, e0 + el, q, Jinv, det, Hd, Fd);
+  __syncthreads();  // the nodal values are consumed: the LDS holds the records from here on
+  // 2. the point's record (slot layout of the records above) into LDS
+  PointOut<float> o;
+  const unsigned fl = point_update<float, true>(a.mp, Hd, Fd, det * Rule::w_rt(q), a.alpha, a.beta, o);
+  if (act && fl) atomicOr(a.flags, fl);
+  HatOut<float> h;
+  to_parent<float, true>(o, Jinv, h);
+  if (act) {
+    float* r = rec + pl * kRecL;
+    sfor<0, kRecL / 4>([&](auto jc) __attribute__((always_inline)) {
+      constexpr int j = decltype(jc)::value;
+      f32x4 v;
+      sfor<0, 4>([&](auto xc) __attribute__((always_inline)) {
+        constexpr int x = decltype(xc)::value;
+        v[x] = record_value<4 * j + x>(h);
+      });
+      *reinterpret_cast<f32x4*>(r + 4 * j) = v;
+    });
+  }
+  __syncthreads();
+  // 3. a lane per task: each wave takes 2 x 7 whole incidences at a time (63
+  //    lanes, two tasks of the same slot each), contracts the element's
+  //    points, and stages the row blocks, 7 at a time, in its LDS buffer; f_a,i
+  //    is the sum of the three component lanes' parts, taken in a fixed order.
+  //    The blocks leave with 16-byte stores of consecutive lanes (whole cache
+  //    lines).
+  const int lane = tid & 63, wave = tid >> 6;
+  float* stg = stage_buf + wave * kRowStage * kRowBlk;
+  const int li = lane / 9, sl = lane - 9 * li, i = sl / 3, k = sl - 3 * i;  // lane 63: li = 7, idle
+  const int n_inc = ne * NEN;
+  constexpr int kGroup = 2 * kRowStage;  // incidences per wave and iteration
+  for (int c0 = kGroup * wave; c0 < n_inc; c0 += kGroup * (kRowThreads / 64)) {  // uniform per wave
+    float acc[2][NEN], facc[2];
+    sfor<0, 2>([&](auto hc) __attribute__((always_inline)) {
+      constexpr int hh = decltype(hc)::value;
+      const int ci = c0 + kRowStage * hh + li;
+      const int cc = (li < kRowStage && ci < n_inc) ? ci : c0;  // idle lanes repeat a live incidence
+      const int le = cc / NEN, an = cc - NEN * le;
+      float dna[16];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const f32x4 x = reinterpret_cast<const f32x4*>(dn + 16 * an)[u];
+        dna[4 * u] = x[0];
+        dna[4 * u + 1] = x[1];
+        dna[4 * u + 2] = x[2];
+        dna[4 * u + 3] = x[3];
+      }
+#pragma unroll
+      for (int b = 0; b < NEN; ++b) acc[hh][b] = 0.0f;
+      facc[hh] = 0.0f;
+      const float* base = rec + le * NQ * kRecL + kSlot * sl;
+      sfor<0, NQ>([&](auto qc) __attribute__((always_inline)) {
+        constexpr int qq = decltype(qc)::value;
+        Slot<float, true> sv;
+        load_slot<float, true>(base + qq * kRecL, sv);
+        contract_point<Rule, float, true, true, qq, NEN>(sv, dna[3 * qq], dna[3 * qq + 1], dna[3 * qq + 2], k,
+                                                         acc[hh], facc[hh]);
+      });
+    });
+    sfor<0, 2>([&](auto hc) __attribute__((always_inline)) {
+      constexpr int hh = decltype(hc)::value;
+      const int g0 = c0 + kRowStage * hh;  // first incidence of this half
+      const float f1 = __shfl_down(facc[hh], 1, 64), f2 = __shfl_down(facc[hh], 2, 64);
+      wave_sync();  // the previous blocks have left the buffer
+      if (li < kRowStage) {
+        float* blk = stg + li * kRowBlk;
+#pragma unroll
+        for (int u = 0; u < NEN / 2; ++u) {
+          f32x2 v;
+          v[0] = acc[hh][2 * u];
+          v[1] = acc[hh][2 * u + 1];
+          *reinterpret_cast<f32x2*>(blk + kSlot * sl + 2 * u) = v;
+        }
+        if (k == 0) blk[9 * kSlot + i] = (facc[hh] + f1) + f2;
+        if (sl < 3) blk[9 * kSlot + 3 + sl] = 0.0f;
+      }
+      wave_sync();
+      const int nb = n_inc - g0 < kRowStage ? n_inc - g0 : kRowStage;  // blocks of this half (may be <= 0)
+#pragma unroll
+      for (int u = 0; u < (kRowStage * kRowBlk / 4 + 63) / 64; ++u) {
+        const int pc = lane + 64 * u, bl = pc / (kRowBlk / 4), pi = pc - bl * (kRowBlk / 4);
+        if (bl < nb)
+          *reinterpret_cast<f32x4*>(rows + (int64_t)pos[g0 + bl] * kRowBlk + 4 * pi) =
+              *reinterpret_cast<const f32x4*>(stg + bl * kRowBlk + 4 * pi);
+      }
+    });
+  }
+}
+
+template <class Rule>
+__global__ __launch_bounds__(kRowThreads) void k_elem_rows(AsmArgs a, const int32_t* incpos, float* rows) {
+  elem_rows_tile<Rule>(a, incpos, rows, blockIdx.x);
+}
+
+// many bodies: every body starts on a workgroup of its own, found by bisection
+template <class Rule>
+__global__ __launch_bounds__(kRowThreads) void k_elem_rows_batch(BatchArgs b) {
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = b.n_bodies - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.bodies[mid].rblock_off <= blk) lo = mid; else hi = mid - 1;
+  }
+  const BatchBody& B = b.bodies[lo];
+  const AsmArgs a = body_args(b, B, lo);
+  elem_rows_tile<Rule>(a, B.incpos, (float*)b.stage + B.blk_inc_off * kRowBlk, blk - B.rblock_off);
+}
+
+// Pass 2 over the row blocks: a lane per (incidence, row i, component k) task
+// of the range loads its ten K entries (three aligned 16-byte pieces of the
+// block, shifted by 2 values for odd slots) and adds them into the range's
+// LDS segment at row + 3 rank_b + k; lanes with k = 0 add the force entry.
+template <bool WANT_F, bool WANT_K, bool ACCUM>
+__device__ __forceinline__ void gather_rows(const GatherArgs& g, int32_t I0, int32_t I1, unsigned char* smem,
+                                            int32_t* pre, int32_t* rowo) {
+  constexpr int TPI = 9;
+  const int tid = threadIdx.x;
+  uint8_t* incn = smem;
+  double* lds = reinterpret_cast<double*>(smem + g.inc_cap);
+  const int nn = I1 - I0;
+  const int64_t row0 = 3LL * I0, row1 = 3LL * I1;
+  const int64_t seg0 = WANT_K ? g.row_off[row0] : 0, seg1 = WANT_K ? g.row_off[row1] : 0;
+  const int nseg = (int)(seg1 - seg0);
+  const int nrow = (int)(row1 - row0);
+  double* lf = lds + nseg;
+  for (int t = tid; t < nseg + nrow; t += blockDim.x) lds[t] = 0.0;
+  const int32_t inc0 = g.inc_off[I0];
+  for (int n = tid; n <= nn; n += blockDim.x) pre[n] = TPI * (g.inc_off[I0 + n] - inc0);
+  if constexpr (WANT_K)
+    for (int rr = tid; rr < nrow; rr += blockDim.x) rowo[rr] = (int32_t)(g.row_off[row0 + rr] - seg0);
+  __syncthreads();
+  for (int n = tid; n < nn; n += blockDim.x)
+    for (int j = pre[n] / TPI; j < pre[n + 1] / TPI; ++j) incn[j] = (uint8_t)n;
+  __syncthreads();
+  const int ntask = pre[nn];
+  const float* blk = reinterpret_cast<const float*>(g.stage);
+  const f32x4* blkv = reinterpret_cast<const f32x4*>(g.stage);
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  for (int t = tid; t < ntask; t += blockDim.x) {
+    const int jl = t / TPI, sl = t - TPI * jl, i = sl / 3, k = sl - 3 * i;
+    const uint32_t j = (uint32_t)(inc0 + jl);
+    const int rl = 3 * incn[jl] + i;
+    if constexpr (WANT_K) {
+      // 16-byte units with 32-bit offsets (checked on the host)
+      const uint32_t p0 = j * (uint32_t)(kRowBlk / 4) + (uint32_t)((kSlot * sl) >> 2);
+      const f32x4 w[3] = {blkv[p0], blkv[p0 + 1], blkv[p0 + 2]};
+      const u32x4 rw = *reinterpret_cast<const u32x4*>(g.rank + (size_t)j * 16);
+      const bool odd = sl & 1;
+      double* dstp = lds + rowo[rl] + k;
+#pragma unroll
+      for (int b = 0; b < 10; ++b) {
+        const float lo = w[b >> 2][b & 3], hi = w[(b + 2) >> 2][(b + 2) & 3];
+        const int rank_b = (int)((rw[b >> 2] >> (8 * (b & 3))) & 255u);
+        atomicAdd(dstp + 3 * rank_b, (double)(odd ? hi : lo));
+      }
+    }
+    if constexpr (WANT_F)
+      if (k == 0) atomicAdd(lf + rl, (double)blk[(size_t)j * kRowBlk + 9 * kSlot + i]);
+  }
+  __syncthreads();
+  if constexpr (WANT_K) {
+    double* out = g.vals + seg0;
+    for (int t = tid; t < nseg; t += blockDim.x) out[t] = ACCUM ? out[t] + lds[t] : lds[t];
+  }
+  if constexpr (WANT_F) {
+    double* out = g.f + row0;
+    for (int t = tid; t < nrow; t += blockDim.x) out[t] = ACCUM ? out[t] + lf[t] : lf[t];
+  }
+}
+
+template <bool WANT_F, bool WANT_K, bool ACCUM>
+__global__ __launch_bounds__(512) void k_gather_rows(GatherArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t pre[kMaxRangeNodes + 1];
+  __shared__ int32_t rowo[kMaxRangeNodes * 3];
+  const int r = remap_tile(blockIdx.x, gridDim.x);
+  gather_rows<WANT_F, WANT_K, ACCUM>(g, g.ranges[r], g.ranges[r + 1], smem, pre, rowo);
+}
+
+__global__ __launch_bounds__(512) void k_gather_rows_batch(BatchArgs b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t pre[kMaxRangeNodes + 1];
+  __shared__ int32_t rowo[kMaxRangeNodes * 3];
+  const int r = remap_tile(blockIdx.x, gridDim.x);
+  const BatchRange br = b.ranges[r];
+  const BatchBody& B = b.bodies[br.body];
+  GatherArgs g{};
+  g.inc_off = B.inc_off;
+  g.row_off = B.row_off;
+  g.rank = B.rank_inc;
+  g.stage = (const float*)b.stage + B.blk_inc_off * kRowBlk;
+  g.f = b.f + B.dof_off;
+  g.vals = b.vals + B.nnz_off;
+  g.inc_cap = b.inc_cap;
+  gather_rows<true, true, false>(g, br.I0, br.I1, smem, pre, rowo);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 int grid_of(int64_t n, int b) { return (int)((n + b - 1) / b); }
@@ -707,6 +968,38 @@ int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals,
   return TLFEA_OK;
 }
 
+// pass 2 over the element row blocks (addressed in 16-byte units with 32-bit offsets)
+int launch_rows_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s) {
+  const bool want_f = f != nullptr, want_k = vals != nullptr;
+  if (m.n_elem * m.n_pn * (int64_t)(kRowBlk / 4) >= ((int64_t)1 << 32)) return TLFEA_ERR_TOO_LARGE;
+  GatherArgs g{};
+  g.ranges = m.d_ranges;
+  g.inc_off = m.d_inc_off;
+  g.row_off = m.d_row_off;
+  g.rank = m.d_rank_inc;
+  g.stage = m.d_stage;
+  g.f = f;
+  g.vals = vals;
+  g.inc_cap = (int)((m.max_range_inc + 15) / 16 * 16);
+  const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows) + g.inc_cap;
+  const dim3 grid((unsigned)m.n_ranges), blk(64 * m.tune.waves);
+#define TLFEA_GATHER(F, K, A)                                              \
+  do {                                                                     \
+    if (int rc = allow_lds(k_gather_rows<F, K, A>, lds)) return rc;        \
+    hipLaunchKernelGGL((k_gather_rows<F, K, A>), grid, blk, lds, s, g);   \
+  } while (0)
+  if (want_k && want_f) {
+    if (accum) TLFEA_GATHER(true, true, true); else TLFEA_GATHER(true, true, false);
+  } else if (want_k) {
+    if (accum) TLFEA_GATHER(false, true, true); else TLFEA_GATHER(false, true, false);
+  } else {
+    if (accum) TLFEA_GATHER(true, false, true); else TLFEA_GATHER(true, false, false);
+  }
+#undef TLFEA_GATHER
+  TLFEA_HIP_CHECK(hipGetLastError());
+  return TLFEA_OK;
+}
+
 template <typename R>
 int launch_points_prec(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s) {
   if (m.elem_type == TLFEA_T10) return launch_points_rule<RuleT10, R>(m, a, want_k, s);
@@ -740,10 +1033,22 @@ __global__ void k_zero(double* __restrict__ p, int64_t n) {
 
 }  // namespace
 
+bool use_rows(const Mesh& m, bool want_k) {
+  static const bool on = [] {
+    const char* v = std::getenv("TLFEA_ELEMENT_ROWS");
+    return !(v && v[0] == '0');
+  }();
+  return on && want_k && m.elem_type == TLFEA_T10 && m.precision == TLFEA_MIXED && m.d_incpos && m.d_rank_inc;
+}
+
 size_t stage_bytes(const Mesh& m, bool want_k) {
+  if (use_rows(m, want_k)) return (size_t)m.n_elem * m.n_pn * kRowBlk * sizeof(float);
   const size_t r = m.precision == TLFEA_MIXED ? sizeof(float) : sizeof(double);
   return (size_t)m.n_elem * m.n_qp * (want_k ? kRecK : kRecF) * r;
 }
+
+size_t row_block_bytes() { return kRowBlk * sizeof(float); }
+int row_elems() { return kRowElems; }
 
 size_t stage_record_bytes(int precision) {
   return (size_t)kRecK * (precision == TLFEA_MIXED ? sizeof(float) : sizeof(double));
@@ -759,6 +1064,15 @@ int launch_zero(double* p, int64_t n, hipStream_t s) {
 }
 
 int launch_points(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s) {
+  if (use_rows(m, want_k)) {
+    const int64_t blocks = (m.n_elem + kRowElems - 1) / kRowElems;
+    if (blocks > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
+    if (blocks > 0)
+      hipLaunchKernelGGL(k_elem_rows<RuleT10>, dim3((unsigned)blocks), dim3(kRowThreads), 0, s, a, m.d_incpos,
+                         (float*)m.d_stage);
+    TLFEA_HIP_CHECK(hipGetLastError());
+    return TLFEA_OK;
+  }
   if (m.precision == TLFEA_MIXED) return launch_points_prec<float>(m, a, want_k, s);
   return launch_points_prec<double>(m, a, want_k, s);
 }
@@ -769,6 +1083,7 @@ int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t
     int rc = f ? launch_zero(f, m.n_dof, s) : TLFEA_OK;
     return (rc || !vals) ? rc : launch_zero(vals, m.nnz, s);
   }
+  if (m.staged == 3) return launch_rows_nodes(m, f, vals, accum, s);
   if (m.precision == TLFEA_MIXED) return launch_nodes_prec<float>(m, f, vals, accum, s);
   return launch_nodes_prec<double>(m, f, vals, accum, s);
 }
@@ -783,6 +1098,16 @@ int launch_force_gather_f64(const Mesh& m, const double* records, double* out, h
 int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tu, const BatchArgs& b,
                  int n_ranges, size_t lds, hipStream_t s) {
   if (n_ranges == 0) return TLFEA_OK;
+  if (b.rows) {
+    if (b.n_rblocks > 0)
+      hipLaunchKernelGGL(k_elem_rows_batch<RuleT10>, dim3((unsigned)b.n_rblocks), dim3(kRowThreads), 0, s, b);
+    TLFEA_HIP_CHECK(hipGetLastError());
+    const size_t lds_all = lds + b.inc_cap;
+    if (int rc = allow_lds(k_gather_rows_batch, lds_all)) return rc;
+    hipLaunchKernelGGL(k_gather_rows_batch, dim3(n_ranges), dim3(64 * tu.waves), lds_all, s, b);
+    TLFEA_HIP_CHECK(hipGetLastError());
+    return TLFEA_OK;
+  }
   const bool mixed = precision == TLFEA_MIXED;
   if (elem_type == TLFEA_T10)
     return mixed ? launch_batch_rule<RuleT10, float>(tu, b, n_ranges, lds, s)

@@ -29,6 +29,8 @@ struct tlfea_batch_s {
   size_t ranges_cap = 0;             // BatchRange entries d_ranges holds
   tlfea::GatherTuning tune;          // pass-2 launch shape the ranges are cut for
   int64_t n_points = 0, n_blocks = 0;
+  int rows = 0;                      // element-row path (T10, mixed)
+  int64_t n_inc = 0, n_rblocks = 0;  // its row blocks and pass-1 workgroups
   size_t lds = 0;
   int inc_cap = 0;
   void* d_stage = nullptr;
@@ -112,6 +114,8 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
   b->elem_type = m0.elem_type;
   b->gl0 = m0.gl[0];
   b->precision = m0.precision;
+  b->rows = 1;
+  for (int i = 0; i < n_bodies; ++i) b->rows &= tlfea::use_rows(meshes[i]->m, true) ? 1 : 0;
   std::vector<BatchBody> bodies(n_bodies);
   b->dof_off.assign(n_bodies + 1, 0);
   b->nnz_off.assign(n_bodies + 1, 0);
@@ -130,6 +134,10 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
     B.rank = m.d_rank;
     B.inc_off = m.d_inc_off;
     B.inc = m.d_inc;
+    B.incpos = m.d_incpos;
+    B.rank_inc = m.d_rank_inc;
+    B.blk_inc_off = b->n_inc;
+    B.rblock_off = b->n_rblocks;
     B.n_elem = m.n_elem;
     B.dof_off = b->dof_off[i];
     B.nnz_off = b->nnz_off[i];
@@ -142,6 +150,13 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
     b->nnz_off[i + 1] = b->nnz_off[i] + m.nnz;
     b->n_points += m.n_elem * m.n_qp;
     b->n_blocks += (m.n_elem * m.n_qp + tlfea::kStageThreads - 1) / tlfea::kStageThreads;
+    b->n_inc += m.n_elem * m.n_pn;
+    b->n_rblocks += (m.n_elem + tlfea::row_elems() - 1) / tlfea::row_elems();
+    // pass 2 addresses a body's row blocks in 16-byte units with 32-bit offsets
+    if (b->rows && m.n_elem * m.n_pn * (int64_t)(tlfea::row_block_bytes() / 16) >= ((int64_t)1 << 32)) {
+      delete b;
+      return TLFEA_ERR_TOO_LARGE;
+    }
     // pass 2 addresses a body's records in 16-byte units with 32-bit offsets
     if (m.n_elem * m.n_qp * (int64_t)(tlfea::stage_record_bytes(b->precision) / 16) >= ((int64_t)1 << 32)) {
       delete b;
@@ -149,8 +164,9 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
     }
     b->meshes.push_back(meshes[i]);
   }
-  if (b->n_blocks > INT32_MAX) { delete b; return TLFEA_ERR_TOO_LARGE; }
-  const size_t stage = (size_t)b->n_points * tlfea::stage_record_bytes(b->precision);
+  if (b->n_blocks > INT32_MAX || b->n_rblocks > INT32_MAX) { delete b; return TLFEA_ERR_TOO_LARGE; }
+  const size_t stage = b->rows ? (size_t)b->n_inc * tlfea::row_block_bytes()
+                               : (size_t)b->n_points * tlfea::stage_record_bytes(b->precision);
   if (hipSetDevice(b->device) != hipSuccess) { delete b; return TLFEA_ERR_HIP; }
   if (hipMalloc(&b->d_bodies, sizeof(BatchBody) * bodies.size()) != hipSuccess ||
       hipMalloc(&b->d_stage, stage > 0 ? stage : 1) != hipSuccess ||
@@ -195,6 +211,8 @@ static BatchArgs batch_args(tlfea_batch_t b, const double* d_q, const double* d_
   a.n_bodies = (int)b->meshes.size();
   a.n_points = b->n_points;
   a.n_blocks = b->n_blocks;
+  a.n_rblocks = b->n_rblocks;
+  a.rows = b->rows;
   a.inc_cap = b->inc_cap;
   a.stage = b->d_stage;
   a.q = d_q;

@@ -109,6 +109,19 @@ __global__ void k_pack_inc(const int32_t* conn, int npn, const int32_t* inc_off,
   }
 }
 
+// For the element-row path (T10): the position of every (element, local node)
+// in the node-sorted incidence list, and that incidence's slot-map row copied
+// into incidence order (16 bytes each).
+__global__ void k_inc_tables(const int32_t* inc, int64_t ninc, int npn, const uint8_t* rank, int32_t* incpos,
+                             uint8_t* rank_inc) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ninc) return;
+  const int32_t v = inc[j];
+  const int64_t ea = (int64_t)(v >> 4) * npn + (v & 15);
+  incpos[ea] = (int32_t)j;
+  *reinterpret_cast<uint4*>(rank_inc + j * 16) = *reinterpret_cast<const uint4*>(rank + ea * 16);
+}
+
 __global__ void k_node_nnz(const int32_t* nadj, int64_t n, int64_t blk, int64_t* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = blk * nadj[i];
@@ -310,6 +323,19 @@ int build_pattern(Mesh& m) {
   // packed, sorted incidence for pass 2
   if (nn > 0)
     hipLaunchKernelGGL(k_pack_inc, dim3(grid_of(nn, 128)), dim3(128), 0, s, m.d_conn, npn, d_inc_off, d_inc, nn);
+  // incidence-ordered tables of the element-row path (T10 only)
+  DevBuf incpos, rank_inc;
+  if (m.elem_type == TLFEA_T10 && ninc > 0) {
+    static_assert(rank_stride(10) == 16, "T10 slot-map rows are 16 bytes");
+    if (hipMalloc(&incpos.p, sizeof(int32_t) * ninc) != hipSuccess || hipMalloc(&rank_inc.p, 16 * ninc) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(d_row_off); (void)hipFree(d_cols); (void)hipFree(d_rank);
+      (void)hipFree(d_adj_off); (void)hipFree(d_adj);
+      return TLFEA_ERR_NOMEM;
+    }
+    hipLaunchKernelGGL(k_inc_tables, dim3(grid_of(ninc, 256)), dim3(256), 0, s, d_inc, ninc, npn, d_rank,
+                       (int32_t*)incpos.p, (uint8_t*)rank_inc.p);
+  }
   std::vector<int32_t> h_inc_off(nn + 1), h_adj_off(nn + 1);
   hipError_t e4 = hipGetLastError();
   hipError_t e5 = hipMemcpy(h_inc_off.data(), d_inc_off, sizeof(int32_t) * (nn + 1), hipMemcpyDeviceToHost);
@@ -332,6 +358,10 @@ int build_pattern(Mesh& m) {
   (void)hipFree(m.d_row_off); (void)hipFree(m.d_cols); (void)hipFree(m.d_rank);
   (void)hipFree(m.d_adj_off); (void)hipFree(m.d_adj); (void)hipFree(m.d_ranges);
   (void)hipFree(m.d_inc_off); (void)hipFree(m.d_inc);
+  (void)hipFree(m.d_incpos); (void)hipFree(m.d_rank_inc);
+  m.d_incpos = (int32_t*)incpos.p;
+  m.d_rank_inc = (uint8_t*)rank_inc.p;
+  incpos.p = rank_inc.p = nullptr;
   m.d_row_off = d_row_off;
   m.d_cols = d_cols;
   m.d_rank = d_rank;

@@ -156,6 +156,8 @@ struct Mesh {
   int32_t* d_inc_off = nullptr;   // n_pnodes + 1, node -> incident elements
   int32_t* d_inc = nullptr;       // (element << 4) | local node index, sorted by element per node
   int32_t* d_ranges = nullptr;    // n_ranges + 1 node boundaries
+  int32_t* d_incpos = nullptr;    // T10: incidence position of every (element, local node)
+  uint8_t* d_rank_inc = nullptr;  // T10: slot-map rows in incidence order (16 bytes each)
   std::vector<int32_t> h_ranges;
   int n_ranges = 0;
   int64_t max_range_values = 0;   // largest LDS segment (CSR values + force rows), in doubles
@@ -167,6 +169,7 @@ struct Mesh {
   void* d_stage = nullptr;        // pass-1 records
   size_t stage_cap = 0;
   int staged = 0;                 // what the last pass 1 left: 0 none, 1 force records, 2 force + tangent
+                                  // records, 3 element row blocks (force + tangent)
   int staged_precision = -1;
 
   bool has_pattern = false;
@@ -227,7 +230,11 @@ struct BatchBody {
   const uint8_t* rank;
   const int32_t* inc_off;
   const int32_t* inc;
+  const int32_t* incpos;     // element-row path: incidence position of every (element, node)
+  const uint8_t* rank_inc;   // element-row path: slot-map rows in incidence order
   int64_t n_elem, dof_off, nnz_off, point_off, block_off;
+  int64_t blk_inc_off;       // element-row path: the body's first row block
+  int64_t rblock_off;        // element-row path: the body's first pass-1 workgroup
   int affine;
   double half_h;
   MatParams mp;
@@ -240,6 +247,8 @@ struct BatchArgs {
   const BatchRange* ranges;
   int n_bodies;
   int64_t n_points, n_blocks;
+  int64_t n_rblocks;  // pass-1 workgroups of the element-row path
+  int rows;           // 1: element-row path (T10, mixed), 0: per-point records
   void* stage;
   const double* q;
   const double* qdot;
@@ -253,8 +262,14 @@ struct BatchArgs {
 MatParams make_params(int material, const double* params, double eta, double lam_v);
 
 // bytes of pass-1 records for a mesh / per record
+// Element-row path: T10 with the tangent in mixed precision (environment
+// TLFEA_ELEMENT_ROWS=0 switches it off).  Pass 1 then leaves one row block per
+// incidence instead of per-point records.
+bool use_rows(const Mesh& m, bool want_k);
 size_t stage_bytes(const Mesh& m, bool want_k);
 size_t stage_record_bytes(int precision);
+size_t row_block_bytes();  // element-row path: bytes per (element, node) row block
+int row_elems();           // element-row path: elements per pass-1 workgroup
 int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tune, const BatchArgs& b,
                  int n_ranges, size_t lds, hipStream_t s);
 

@@ -102,7 +102,7 @@ def report(base: str, out_json: str, shape: dict) -> dict:
         factor = COPY_BYTES / (copy * 1024.0)
         res[counter.lower() + "_factor"] = factor
         for k, vals in per.items():
-            if not (k.startswith("k_stage") or k.startswith("k_gather")):
+            if not (k.startswith("k_stage") or k.startswith("k_gather") or k.startswith("k_elem")):
                 continue
             mean_kib = sum(vals) / len(vals)
             e = res["kernels"].setdefault(k, {})

@@ -223,7 +223,8 @@ int tlfea_get_runtime_flags(tlfea_mesh_t mesh, uint32_t* flags);
  * Not a step of the method: the shape decides how the nodes are cut into
  * ranges (each range is one workgroup whose CSR rows are one contiguous
  * segment held in LDS) and how many waves work on a range.  Every shape gives
- * the same result up to rounding order.  The default is {4, 768, 4096}
+ * the same result up to rounding order.  The default is {4, 768, 2048} for
+ * T10 meshes created in mixed precision and {4, 768, 4096} otherwise
  * (environment TLFEA_GATHER_WAVES / TLFEA_RANGE_TASKS / TLFEA_RANGE_VALUES
  * override it when the pattern is built).
  * ------------------------------------------------------------------------- */

@@ -340,7 +340,7 @@ int build_pattern(Mesh& m) {
   hipError_t e4 = hipGetLastError();
   hipError_t e5 = hipMemcpy(h_inc_off.data(), d_inc_off, sizeof(int32_t) * (nn + 1), hipMemcpyDeviceToHost);
   hipError_t e6 = hipMemcpy(h_adj_off.data(), d_adj_off, sizeof(int32_t) * (nn + 1), hipMemcpyDeviceToHost);
-  const GatherTuning tune = gather_tuning();
+  const GatherTuning tune = gather_tuning(m);
   RangePlan plan = plan_ranges(h_inc_off, h_adj_off, mc, tune);
   int32_t* d_ranges = nullptr;
   hipError_t e7 = hipMalloc(&d_ranges, sizeof(int32_t) * plan.ranges.size());
@@ -392,8 +392,9 @@ static int env_int(const char* name, int fallback, int lo, int hi) {
   return (x < lo || x > hi) ? fallback : (int)x;
 }
 
-GatherTuning gather_tuning() {
+GatherTuning gather_tuning(const Mesh& m) {
   GatherTuning t;
+  if (m.elem_type == TLFEA_T10 && m.precision == TLFEA_MIXED) t.range_values = 2048;
   t.waves = env_int("TLFEA_GATHER_WAVES", t.waves, 1, 8);
   t.range_tasks = env_int("TLFEA_RANGE_TASKS", t.range_tasks, 1, 1 << 20);
   t.range_values = env_int("TLFEA_RANGE_VALUES", t.range_values, 1, 12 * 1024);

@@ -38,9 +38,11 @@ struct GatherTuning {
   int range_tasks = 768;
   int range_values = 4096;
 };
-// defaults, overridden by TLFEA_GATHER_WAVES / TLFEA_RANGE_TASKS /
-// TLFEA_RANGE_VALUES when set (tuning sweeps)
-GatherTuning gather_tuning();
+// defaults ({4, 768, 2048} for T10 meshes created in mixed precision, whose
+// tangent takes the element-row path, else {4, 768, 4096}), overridden by
+// TLFEA_GATHER_WAVES / TLFEA_RANGE_TASKS / TLFEA_RANGE_VALUES when set
+struct Mesh;
+GatherTuning gather_tuning(const Mesh& m);
 // a range's LDS segment (CSR values + force rows) must stay below this
 constexpr int64_t kMaxSegmentBytes = 96 * 1024;
 

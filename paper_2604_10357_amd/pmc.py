@@ -42,7 +42,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-DEFAULT_SHAPE = {"waves": 4, "range_tasks": 768, "range_values": 4096}
+DEFAULT_SHAPE = {"waves": 4, "range_tasks": 768, "range_values": 2048}  # T10 built in mixed precision
 
 
 def _shape(args) -> dict:

@@ -626,7 +626,7 @@ __global__ __launch_bounds__(512) void k_gather_batch(BatchArgs b) {
   const int r = remap_tile(blockIdx.x, gridDim.x);
   const BatchRange br = b.ranges[r];
   const BatchBody& B = b.bodies[br.body];
-  GatherArgs g;
+  GatherArgs g{};
   g.ranges = nullptr;
   g.inc_off = B.inc_off;
   g.inc = B.inc;

@@ -135,9 +135,32 @@ def cpu_baseline(wl, f_gpu, vals_gpu, ro, cols, h, budget_s=12.0):
         kmax = max(kmax, np.abs(v_ref[a:b]).max())
     errs["f"] = float(ef)
     errs["K"] = float(kd / kmax)
+    cpu = cpu_model()
     base = {"value": n / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} of {n_el} elements, fused f + K, FP64 C oracle, {dt:.1f} s single-threaded"}
-    return base, errs, len(rows)
+            "sample": f"first {n} of {n_el} elements, fused f + K, FP64 C oracle, {dt:.1f} s single-threaded",
+            "cpu": cpu}
+    # the same sample through the oracle's timing-only OpenMP form, all host threads
+    t0 = time.perf_counter()
+    _, _, threads = oracle.assemble_omp(om, omat, wl.q, wl.qdot, h, 1.0, pat)
+    dt_omp = time.perf_counter() - t0
+    base_omp = {"value": n / dt_omp, "unit": "elements/s", "cores": threads, "kind": "oracle_openmp",
+                "sample": f"first {n} of {n_el} elements, fused f + K, FP64 C oracle with an OpenMP element loop "
+                          f"and atomic scatter, {dt_omp:.2f} s on {threads} threads", "cpu": cpu}
+    return base, base_omp, errs, len(rows)
+
+
+def cpu_model():
+    """The host CPU's model name and logical CPU count, as the OS reports them."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name} ({os.cpu_count()} logical CPUs)"
 
 
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
@@ -277,8 +300,9 @@ def bench_mesh(args, torch, wl, wname):
         out["vjp_ms"] = time_calls(lambda: mesh.vjp(q, qd, w), max(3, args.steps // 4), torch)
         out["copy_GBs"] = copy_bandwidth(torch)
     if not args.no_cpu_baseline:
-        base, errs, nrows = cpu_baseline(wl, f_h, v_h, ro, cols, h)
+        base, base_omp, errs, nrows = cpu_baseline(wl, f_h, v_h, ro, cols, h)
         out["cpu_baseline"] = base
+        out["cpu_baseline_openmp"] = base_omp
         out["error_vs_oracle"] = dict(errs, rows=nrows, precision=args.precision,
                                       gate=1e-5 if args.precision == "mixed" else 1e-12)
     mesh.close()

@@ -16,6 +16,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "tlfea_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+SRC_OMP = os.path.join(HERE, "tlfea_oracle_omp.c")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 T10 = 1
 ANCF3443 = 2
@@ -24,11 +26,18 @@ MR = 2
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (single-threaded FP64 C, -O2, no fast-math)."""
+    """Compile the oracle with gcc (single-threaded FP64 C, -O2, no fast-math),
+    and its timing-only OpenMP form (the same source plus a threaded loop)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
+    newest = max(os.path.getmtime(SRC), os.path.getmtime(SRC_OMP))
+    if force or not os.path.exists(LIB_OMP) or os.path.getmtime(LIB_OMP) < newest:
+        tmp = LIB_OMP + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-o", tmp, SRC_OMP,
+                               "-lm"])
+        os.replace(tmp, LIB_OMP)
     return LIB
 
 
@@ -266,3 +275,31 @@ def vjp(mesh: Mesh, mat, q, qdot, w):
 def energy(mesh: Mesh, mat, q):
     q = np.ascontiguousarray(q, dtype=np.float64)
     return lib().orc_energy(ctypes.byref(mesh.s), ctypes.byref(mat), _dp(q))
+
+
+_lib_omp = None
+
+
+def assemble_omp(mesh: Mesh, mat, q, qdot, alpha, beta, pattern):
+    """Timing-only OpenMP form of the fused f + K (atomic scatter over threads);
+    returns (f, vals, threads used)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(LIB_OMP):
+            build(force=False)
+        L = ctypes.CDLL(LIB_OMP)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.orc_assemble_omp.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Material), dp, dp, ctypes.c_double,
+                                       ctypes.c_double, dp, ip, ip, dp]
+        L.orc_assemble_omp.restype = ctypes.c_int
+        L.orc_omp_threads.restype = ctypes.c_int
+        _lib_omp = L
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    qd = None if qdot is None else np.ascontiguousarray(qdot, dtype=np.float64)
+    row_off, cols = pattern
+    f = np.zeros(mesh.n_dof)
+    vals = np.zeros(cols.shape[0])
+    _chk(_lib_omp.orc_assemble_omp(ctypes.byref(mesh.s), ctypes.byref(mat), _dp(q), _dp(qd), alpha, beta, _dp(f),
+                                   _ip(row_off), _ip(cols), _dp(vals)), "assemble_omp")
+    return f, vals, int(_lib_omp.orc_omp_threads())

@@ -93,3 +93,19 @@ def test_generator_is_seeded():
     assert np.array_equal(a.q, b.q) and np.array_equal(a.qdot, b.qdot) and np.array_equal(a.w, b.w)
     c = W.config1(seed=7)
     assert not np.array_equal(a.q, c.q)
+
+
+def test_openmp_timing_form_matches_the_oracle():
+    """The threaded form the benchmark times on all host cores computes the
+    same sums (only the order of the scatter differs)."""
+    import oracle
+
+    wl = W.t10_beam(3, 2, 2, 61, "omp_check", lx=0.3, ly=0.2, lz=0.2)
+    om = oracle.Mesh.of(wl.mesh)
+    omat = oracle.material_of(wl.material)
+    pat = oracle.csr_pattern(om)
+    f1, v1 = oracle.assemble(om, omat, wl.q, wl.qdot, 1e-3, 1.0, pattern=pat)
+    f2, v2, threads = oracle.assemble_omp(om, omat, wl.q, wl.qdot, 1e-3, 1.0, pat)
+    assert threads >= 1
+    assert np.abs(f2 - f1).max() <= 1e-13 * np.abs(f1).max()
+    assert np.abs(v2 - v1).max() <= 1e-13 * np.abs(v1).max()

@@ -85,6 +85,10 @@ def lib():
         L.orc_vjp.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Material), dp, dp, dp, dp, dp, dp]
         L.orc_energy.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Material), dp]
         L.orc_energy.restype = ctypes.c_double
+        L.orc_element_mass.argtypes = [ctypes.POINTER(_Mesh), ctypes.c_int, ctypes.c_double, dp]
+        L.orc_mass_assemble.argtypes = [ctypes.POINTER(_Mesh), ctypes.c_double, ip, ip, dp]
+        L.orc_gradient.argtypes = [ctypes.c_int, ip, ip, dp, dp, dp, dp, dp, ctypes.c_double, dp]
+        L.orc_gradient.restype = None
         _lib = L
     return _lib
 
@@ -247,6 +251,37 @@ def assemble(mesh: Mesh, mat, q, qdot=None, alpha=1.0, beta=0.0, elems=None, pat
     _chk(lib().orc_assemble(ctypes.byref(mesh.s), ctypes.byref(mat), _dp(q), _dp(qd), alpha, beta,
                             _ip(el), n_list, _dp(f), _ip(row_off), _ip(cols), _dp(vals)), "assemble")
     return f, vals
+
+
+def element_mass(mesh: Mesh, e, rho):
+    """Consistent element mass m_ab = int rho N_a N_b dV (n_en x n_en), Sec. 4.1."""
+    n = mesh.n_en
+    m = np.zeros((n, n))
+    _chk(lib().orc_element_mass(ctypes.byref(mesh.s), int(e), float(rho), _dp(m)), "element_mass")
+    return m
+
+
+def mass_csr(mesh: Mesh, rho, pattern=None):
+    """DOF-level CSR values of M = [m_ab I_3] on the mesh pattern."""
+    if pattern is None:
+        pattern = csr_pattern(mesh)
+    row_off, cols = pattern
+    vals = np.zeros(cols.shape[0])
+    _chk(lib().orc_mass_assemble(ctypes.byref(mesh.s), float(rho), _ip(row_off), _ip(cols), _dp(vals)),
+         "mass_assemble")
+    return vals
+
+
+def gradient(pattern, mvals, v, v_prev, f_int, f_ext, h):
+    """g = M (v - v_prev) / h + f_int - f_ext (Sec. 4.4.1, Eq. grad_L, no constraints)."""
+    row_off, cols = pattern
+    n = row_off.shape[0] - 1
+    arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (mvals, v, v_prev, f_int)]
+    fe = None if f_ext is None else np.ascontiguousarray(f_ext, dtype=np.float64)
+    g = np.zeros(n)
+    lib().orc_gradient(n, _ip(row_off), _ip(cols), _dp(arr[0]), _dp(arr[1]), _dp(arr[2]), _dp(arr[3]), _dp(fe),
+                       float(h), _dp(g))
+    return g
 
 
 def slot_map(mesh: Mesh, pattern, e0=0, ne=None):

@@ -859,3 +859,133 @@ double orc_energy(const orc_mesh* mesh, const orc_material* mat, const double* q
     }
   return total;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Mass, gradient (Sec. 4.1: m_ij = int rho s_i s_j dV, M_e = [m_ij I_3];     */
+/* Sec. 4.4.1, Eq. grad_L; Sec. 4.4.2, Eq. hessian)                           */
+/* ------------------------------------------------------------------------- */
+
+static long long factorial(int n) {
+  long long f = 1;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+/* T10 shape function a as a homogeneous quadratic in the barycentric
+ * coordinates (using L0 + L1 + L2 + L3 = 1): N_a = sum_ij Q[i][j] L_i L_j */
+static void t10_quadratic(int a, double Q[4][4]) {
+  static const int edges[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) Q[i][j] = 0.0;
+  if (a < 4) {
+    /* L_c (2 L_c - 1) = 2 L_c^2 - L_c sum_k L_k */
+    for (int k = 0; k < 4; ++k) {
+      Q[a][k] -= 0.5;
+      Q[k][a] -= 0.5;
+    }
+    Q[a][a] += 2.0;
+  } else {
+    int c = edges[a - 4][0], d = edges[a - 4][1];
+    Q[c][d] = 2.0;
+    Q[d][c] = 2.0;
+  }
+}
+
+/* consistent element mass (scalar m_ab, n_en x n_en).  T10: exact integral over
+ * a straight-sided tetrahedron, int L0^a0 L1^a1 L2^a2 L3^a3 dV = det J0 a0! a1!
+ * a2! a3! / (a0+a1+a2+a3+3)!; curved elements are rejected.  ANCF3443: Gauss-
+ * Legendre 4 x 4 x 2 in the parent box (exact for the element's polynomial
+ * products on an affine reference geometry). */
+int orc_element_mass(const orc_mesh* mesh, int e, double rho, double* m) {
+  int nen = orc_n_en(mesh->elem_type);
+  if (nen == 0) return ORC_EINVAL;
+  for (int t = 0; t < nen * nen; ++t) m[t] = 0.0;
+  if (mesh->elem_type == ORC_T10) {
+    double g[30], det0, det1;
+    const double c0[3] = {0.25, 0.25, 0.25}, c1[3] = {0.1, 0.2, 0.3};
+    int rc = qp_geometry(mesh, e, c0, 1.0, &det0, g);
+    if (rc != ORC_OK) return rc;
+    rc = qp_geometry(mesh, e, c1, 1.0, &det1, g);
+    if (rc != ORC_OK) return rc;
+    if (fabs(det1 - det0) > 1e-12 * fabs(det0)) return ORC_EINVAL;  /* not straight-sided */
+    double Q[10][4][4];
+    for (int a = 0; a < 10; ++a) t10_quadratic(a, Q[a]);
+    for (int a = 0; a < 10; ++a)
+      for (int b = 0; b < 10; ++b) {
+        double sum = 0.0;
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j)
+            for (int k = 0; k < 4; ++k)
+              for (int l = 0; l < 4; ++l) {
+                double c = Q[a][i][j] * Q[b][k][l];
+                if (c == 0.0) continue;
+                int al[4] = {0, 0, 0, 0};
+                al[i]++; al[j]++; al[k]++; al[l]++;
+                sum += c * (double)(factorial(al[0]) * factorial(al[1]) * factorial(al[2]) * factorial(al[3])) /
+                       (double)factorial(7);
+              }
+        m[10 * a + b] = rho * det0 * sum;
+      }
+    return ORC_OK;
+  }
+  /* ANCF3443 */
+  double x4[4], w4[4], x2[2], w2[2];
+  orc_gauss_legendre(4, x4, w4);
+  orc_gauss_legendre(2, x2, w2);
+  const double* X = mesh->X;
+  int n0 = mesh->conn[4 * e], n1 = mesh->conn[4 * e + 1], n3 = mesh->conn[4 * e + 3];
+  double lx = 0, ly = 0;
+  for (int d = 0; d < 3; ++d) {
+    double a = X[3 * (4 * n1) + d] - X[3 * (4 * n0) + d];
+    double b = X[3 * (4 * n3) + d] - X[3 * (4 * n0) + d];
+    lx += a * a;
+    ly += b * b;
+  }
+  lx = sqrt(lx);
+  ly = sqrt(ly);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      for (int k = 0; k < 2; ++k) {
+        double xi[3] = {x4[i], x4[j], x2[k]}, S[16], dS[48], g[48], dV;
+        if (orc_ancf3443_shape(xi, lx, ly, mesh->thickness, S, dS) != ORC_OK) return ORC_EDEGENERATE;
+        int rc = qp_geometry(mesh, e, xi, w4[i] * w4[j] * w2[k], &dV, g);
+        if (rc != ORC_OK) return rc;
+        for (int a = 0; a < 16; ++a)
+          for (int b = 0; b < 16; ++b) m[16 * a + b] += rho * S[a] * S[b] * dV;
+      }
+  return ORC_OK;
+}
+
+/* accumulate (+=) the DOF-level mass M_e = [m_ab I_3] of every element into
+ * CSR values on the mesh pattern (off-diagonal entries of a 3x3 block get 0) */
+int orc_mass_assemble(const orc_mesh* mesh, double rho, const int* row_off, const int* cols,
+                      double* vals) {
+  int nen = orc_n_en(mesh->elem_type);
+  double* m = (double*)malloc(sizeof(double) * nen * nen);
+  int rc = ORC_OK;
+  for (int e = 0; e < mesh->n_elem && rc == ORC_OK; ++e) {
+    rc = orc_element_mass(mesh, e, rho, m);
+    if (rc != ORC_OK) break;
+    for (int a = 0; a < nen; ++a)
+      for (int b = 0; b < nen; ++b)
+        for (int d = 0; d < 3; ++d) {
+          long long pos = find_col(row_off, cols, 3 * coef_of(mesh, e, a) + d, 3 * coef_of(mesh, e, b) + d);
+          if (pos < 0) { rc = ORC_ENOTFOUND; break; }
+          vals[pos] += m[nen * a + b];
+        }
+  }
+  free(m);
+  return rc;
+}
+
+/* Eq. grad_L without constraint terms: g = M (v - v_prev) / h + f_int - f_ext,
+ * M given as DOF-level CSR values (f_ext may be NULL); overwrites g */
+void orc_gradient(int n_dof, const int* row_off, const int* cols, const double* mvals, const double* v,
+                  const double* v_prev, const double* f_int, const double* f_ext, double h, double* g) {
+  for (int r = 0; r < n_dof; ++r) {
+    double s = 0.0;
+    for (int k = row_off[r]; k < row_off[r + 1]; ++k) s += mvals[k] * (v[cols[k]] - v_prev[cols[k]]);
+    g[r] = s / h + f_int[r] - (f_ext ? f_ext[r] : 0.0);
+  }
+}
+

@@ -99,6 +99,16 @@ int orc_slot_map(const orc_mesh* mesh, const int* row_off, const int* cols, int 
 int orc_vjp(const orc_mesh* mesh, const orc_material* mat, const double* q, const double* qdot,
             const double* w, double* gq, double* gqdot, double* gparams);
 
+/* consistent element mass m_ab = int rho N_a N_b dV (n_en x n_en; Sec. 4.1):
+ * T10 exact on straight-sided elements (ORC_EINVAL if curved), ANCF3443 by
+ * Gauss-Legendre 4x4x2 */
+int orc_element_mass(const orc_mesh* mesh, int e, double rho, double* m);
+/* accumulate (+=) M = [m_ab I_3] into CSR values of the mesh pattern */
+int orc_mass_assemble(const orc_mesh* mesh, double rho, const int* row_off, const int* cols,
+                      double* vals);
+/* g = M (v - v_prev) / h + f_int - f_ext (Sec. 4.4.1, Eq. grad_L, no constraints) */
+void orc_gradient(int n_dof, const int* row_off, const int* cols, const double* mvals, const double* v,
+                  const double* v_prev, const double* f_int, const double* f_ext, double h, double* g);
 /* total elastic energy sum_e sum_q dV W(F) */
 double orc_energy(const orc_mesh* mesh, const orc_material* mat, const double* q);
 

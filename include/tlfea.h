@@ -214,6 +214,36 @@ int tlfea_internal_force_vjp(tlfea_mesh_t mesh, const double* d_q, const double*
                              const double* d_w, double* d_gq, double* d_gqdot, double* d_gparam,
                              void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Newton step pieces (T10 meshes of straight-sided elements).
+ * ------------------------------------------------------------------------- */
+/* Build the consistent mass matrix once (Sec. 4.1: m_ij = int rho N_i N_j dV
+ * over each element, M_e = [m_ij I_3], assembled over the elements): exact
+ * integrals of the quadratic shape functions, float64, kept on the device per
+ * pair of adjacent nodes.  density > 0.  Needs the CSR pattern
+ * (TLFEA_ERR_NO_PATTERN); TLFEA_ERR_UNSUPPORTED for ANCF meshes and for T10
+ * meshes with curved elements.  Synchronises; a new pattern drops the mass. */
+int tlfea_build_mass(tlfea_mesh_t mesh, double density);
+/* M as DOF-level CSR values on the mesh pattern (nnz float64, device): row
+ * 3I+d holds M_IJ at column 3J+d and 0 at the other columns of the block.
+ * TLFEA_ERR_INVALID before tlfea_build_mass. */
+int tlfea_get_mass(tlfea_mesh_t mesh, double* d_vals, void* stream);
+/* f_int and the Newton matrix H = M/h + h K_t (Sec. 4.4.2, Eq. hessian,
+ * without constraint terms), K_t being the tangent with (alpha, beta) =
+ * (h, 1): H = M/h + h df/dq + df/dqdot, the Jacobian in v of Eq. grad_L at
+ * q = q_n + h v, qdot = v.  Overwrites d_f (may be NULL) and d_vals (nnz).
+ * The mass term enters the per-range sums of the second pass, so H costs one
+ * write like K.  h > 0.  TLFEA_ERR_INVALID before tlfea_build_mass. */
+int tlfea_assemble_newton(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double h,
+                          double* d_f, double* d_vals, void* stream);
+/* g = M (v - v_prev)/h + f_int - f_ext (Sec. 4.4.1, Eq. grad_L, without
+ * constraint terms), n_dof float64 each, device; d_f_ext may be NULL (0).
+ * A lane per node over its mass row; overwrites d_g.  h > 0.
+ * TLFEA_ERR_INVALID before tlfea_build_mass. */
+int tlfea_newton_gradient(tlfea_mesh_t mesh, const double* d_v, const double* d_v_prev,
+                          const double* d_f_int, const double* d_f_ext, double h, double* d_g,
+                          void* stream);
+
 /* Read (and synchronise on the mesh's last stream) the runtime flag bits,
  * then clear them. */
 int tlfea_get_runtime_flags(tlfea_mesh_t mesh, uint32_t* flags);

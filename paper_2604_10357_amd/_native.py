@@ -29,6 +29,7 @@ EXPORTED = [
     "tlfea_batch_destroy", "tlfea_batch_offsets", "tlfea_batch_assemble", "tlfea_batch_assemble_loop",
     "tlfea_mesh_set_gather_shape", "tlfea_mesh_get_gather_shape", "tlfea_mesh_autotune",
     "tlfea_batch_set_gather_shape", "tlfea_batch_get_gather_shape", "tlfea_batch_autotune",
+    "tlfea_build_mass", "tlfea_get_mass", "tlfea_assemble_newton", "tlfea_newton_gradient",
 ]
 
 
@@ -107,6 +108,10 @@ def lib() -> ctypes.CDLL:
         "tlfea_batch_set_gather_shape": ([vp, P(GatherShape)], ctypes.c_int),
         "tlfea_batch_get_gather_shape": ([vp, P(GatherShape), P(i64)], ctypes.c_int),
         "tlfea_batch_autotune": ([vp, vp, vp, vp, vp, vp, i32, vp, P(GatherShape), P(ctypes.c_float)], ctypes.c_int),
+        "tlfea_build_mass": ([vp, dbl], ctypes.c_int),
+        "tlfea_get_mass": ([vp, vp, vp], ctypes.c_int),
+        "tlfea_assemble_newton": ([vp, vp, vp, dbl, vp, vp, vp], ctypes.c_int),
+        "tlfea_newton_gradient": ([vp, vp, vp, vp, vp, dbl, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

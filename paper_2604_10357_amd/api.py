@@ -172,6 +172,33 @@ class TLMesh:
                 "tlfea_internal_force_vjp")
         return gq, gqd, gp
 
+    def build_mass(self, density: float):
+        """Consistent mass matrix (T10, straight-sided elements), built once."""
+        N.check(N.lib().tlfea_build_mass(self._h, float(density)), "tlfea_build_mass")
+
+    def mass_values(self, out=None, device="cuda"):
+        """M as DOF-level CSR values on the mesh pattern."""
+        out = torch.empty(self.nnz, dtype=torch.float64, device=device) if out is None else out
+        N.check(N.lib().tlfea_get_mass(self._h, _ptr(out, n=self.nnz), _stream()), "tlfea_get_mass")
+        return out
+
+    def assemble_newton(self, q, qdot, h: float, f=None, vals=None):
+        """f_int and H = M/h + h df/dq + df/dqdot."""
+        f = torch.empty(self.n_dof, dtype=torch.float64, device=q.device) if f is None else f
+        vals = torch.empty(self.nnz, dtype=torch.float64, device=q.device) if vals is None else vals
+        N.check(N.lib().tlfea_assemble_newton(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof), float(h),
+                                              _ptr(f, n=self.n_dof), _ptr(vals, n=self.nnz), _stream()),
+                "tlfea_assemble_newton")
+        return f, vals
+
+    def newton_gradient(self, v, v_prev, f_int, f_ext, h: float, out=None):
+        """g = M (v - v_prev)/h + f_int - f_ext (f_ext may be None)."""
+        out = torch.empty(self.n_dof, dtype=torch.float64, device=v.device) if out is None else out
+        N.check(N.lib().tlfea_newton_gradient(self._h, _ptr(v, n=self.n_dof), _ptr(v_prev, n=self.n_dof),
+                                              _ptr(f_int, n=self.n_dof), _ptr(f_ext, n=self.n_dof), float(h),
+                                              _ptr(out, n=self.n_dof), _stream()), "tlfea_newton_gradient")
+        return out
+
     def set_gather_shape(self, waves: int, range_tasks: int, range_values: int):
         sh = N.GatherShape(waves, range_tasks, range_values)
         N.check(N.lib().tlfea_mesh_set_gather_shape(self._h, ctypes.byref(sh)), "tlfea_mesh_set_gather_shape")

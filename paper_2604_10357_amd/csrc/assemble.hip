@@ -378,6 +378,24 @@ __device__ __forceinline__ void contract_point_rt(const Slot<R, WANT_K>& s, int 
   }
 }
 
+// Newton matrix (Sec. 4.4.2, Eq. hessian): the LDS segment of a range starts
+// from M_IJ / h on the diagonal entries (d, d) of every 3x3 block (I, J) of
+// its rows (T10: one coefficient per node; the segment is zero elsewhere).
+// Runs after the segment is cleared and before any contribution is added.
+__device__ __forceinline__ void add_mass_term(const GatherArgs& g, int32_t I0, int nn, double* lds,
+                                              const int32_t* rowo) {
+  if (!g.mass) return;
+  for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+    const int32_t k0 = g.adj_off[I0 + n], k1 = g.adj_off[I0 + n + 1];
+    for (int32_t k = k0; k < k1; ++k) {
+      const double v = g.mass[k] * g.inv_h;
+      const int r = k - k0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) lds[rowo[3 * n + d] + 3 * r + d] = v;
+    }
+  }
+}
+
 template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM>
 __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, int32_t I1, unsigned char* smem,
                                              int32_t* pre, int32_t* rowo) {
@@ -423,6 +441,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   // range-local node of every incidence (nodes < kMaxRangeNodes fit a byte)
   for (int n = tid; n < nn; n += blockDim.x)
     for (int j = pre[n] / TPI; j < pre[n + 1] / TPI; ++j) incn[j] = (uint8_t)n;
+  if constexpr (WANT_K && MC == 1) add_mass_term(g, I0, nn, lds, rowo);
   __syncthreads();
   const int ntask = pre[nn];
   // Tasks are ordered (node, incidence, kind, row, component): task t belongs
@@ -659,6 +678,9 @@ constexpr int kRowElems = 25;     // elements per pass-1 workgroup
 constexpr int kRowThreads = 128;  // 125 point lanes
 constexpr int kRecL = 92;         // LDS record stride in values (a 16-byte multiple)
 constexpr int kRowStage = 7;      // incidences a wave contracts at a time (63 of its lanes)
+constexpr int kDnL = 20;          // LDS stride of a node's gradient row (16 used; 20 keeps the rows
+                                  // of the ten nodes on different banks)
+constexpr int kStgL = 100;        // LDS stride of a staged row block (96 used; spreads the banks)
 
 template <class Rule>
 __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* __restrict__ incpos,
@@ -668,9 +690,9 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
   static_assert(kRowElems * NQ <= kRowThreads, "a lane per point");
   static_assert(kRowThreads % 64 == 0 && 9 * kRowStage <= 64, "a wave stages whole incidences");
   __shared__ __align__(16) float rec[kRowElems * NQ * kRecL];
-  __shared__ __align__(16) float dn[NEN * 16];   // parent gradients of every node at every point
+  __shared__ __align__(16) float dn[NEN * kDnL];  // parent gradients of every node at every point
   __shared__ int32_t pos[kRowElems * NEN];         // incidence position of every (element, node)
-  __shared__ __align__(16) float stage_buf[(kRowThreads / 64) * kRowStage * kRowBlk];  // per-wave row blocks
+  __shared__ __align__(16) float stage_buf[(kRowThreads / 64) * kRowStage * kStgL];  // per-wave row blocks
   static_assert(kRowElems * NEN * 6 * sizeof(double) <= sizeof(rec), "nodal values fit the record area");
   const int tid = threadIdx.x;
   const int64_t e0 = blk * kRowElems;
@@ -679,7 +701,7 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
   double* nod = reinterpret_cast<double*>(rec);
   gather_nodal<Rule>(a, e0, ne, nod);
   for (int idx = tid; idx < ne * NEN; idx += kRowThreads) pos[idx] = incpos[e0 * NPN + idx];
-  for (int idx = tid; idx < NEN * 16; idx += kRowThreads) dn[idx] = Rule::template rows<float>(idx / 16)[idx % 16];
+  for (int idx = tid; idx < NEN * 16; idx += kRowThreads) dn[kDnL * (idx / 16) + idx % 16] = Rule::template rows<float>(idx / 16)[idx % 16];
   __syncthreads();
   const bool act = tid < ne * NQ;
   const int pl = act ? tid : 0;  // idle lanes evaluate point 0 and store nothing
@@ -713,7 +735,7 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
   //    The blocks leave with 16-byte stores of consecutive lanes (whole cache
   //    lines).
   const int lane = tid & 63, wave = tid >> 6;
-  float* stg = stage_buf + wave * kRowStage * kRowBlk;
+  float* stg = stage_buf + wave * kRowStage * kStgL;
   const int li = lane / 9, sl = lane - 9 * li, i = sl / 3, k = sl - 3 * i;  // lane 63: li = 7, idle
   const int n_inc = ne * NEN;
   constexpr int kGroup = 2 * kRowStage;  // incidences per wave and iteration
@@ -727,7 +749,7 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
       float dna[16];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const f32x4 x = reinterpret_cast<const f32x4*>(dn + 16 * an)[u];
+        const f32x4 x = reinterpret_cast<const f32x4*>(dn + kDnL * an)[u];
         dna[4 * u] = x[0];
         dna[4 * u + 1] = x[1];
         dna[4 * u + 2] = x[2];
@@ -751,7 +773,7 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
       const float f1 = __shfl_down(facc[hh], 1, 64), f2 = __shfl_down(facc[hh], 2, 64);
       wave_sync();  // the previous blocks have left the buffer
       if (li < kRowStage) {
-        float* blk = stg + li * kRowBlk;
+        float* blk = stg + li * kStgL;
 #pragma unroll
         for (int u = 0; u < NEN / 2; ++u) {
           f32x2 v;
@@ -769,7 +791,7 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
         const int pc = lane + 64 * u, bl = pc / (kRowBlk / 4), pi = pc - bl * (kRowBlk / 4);
         if (bl < nb)
           *reinterpret_cast<f32x4*>(rows + (int64_t)pos[g0 + bl] * kRowBlk + 4 * pi) =
-              *reinterpret_cast<const f32x4*>(stg + bl * kRowBlk + 4 * pi);
+              *reinterpret_cast<const f32x4*>(stg + bl * kStgL + 4 * pi);
       }
     });
   }
@@ -819,6 +841,7 @@ __device__ __forceinline__ void gather_rows(const GatherArgs& g, int32_t I0, int
   __syncthreads();
   for (int n = tid; n < nn; n += blockDim.x)
     for (int j = pre[n] / TPI; j < pre[n + 1] / TPI; ++j) incn[j] = (uint8_t)n;
+  if constexpr (WANT_K) add_mass_term(g, I0, nn, lds, rowo);
   __syncthreads();
   const int ntask = pre[nn];
   const float* blk = reinterpret_cast<const float*>(g.stage);
@@ -933,7 +956,8 @@ bool records_addressable(int64_t n_elem, bool want_k) {
 }
 
 template <class Rule, typename R>
-int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals, bool accum, hipStream_t s) {
+int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals, bool accum, hipStream_t s,
+                      const MassTerm& mt = MassTerm{}) {
   const bool want_f = f != nullptr, want_k = vals != nullptr;
   if (!records_addressable<Rule, R>(m.n_elem, want_k)) return TLFEA_ERR_TOO_LARGE;
   GatherArgs g{};
@@ -947,6 +971,9 @@ int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals,
   g.stage = stage;
   g.f = f;
   g.vals = vals;
+  g.mass = mt.mass;
+  g.adj_off = m.d_adj_off;
+  g.inv_h = mt.inv_h;
   g.inc_cap = (int)((m.max_range_inc + 15) / 16 * 16);
   const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows) + g.inc_cap +
                      (size_t)m.tune.waves * (want_k ? wave_buf_bytes<Rule, R, true>() : wave_buf_bytes<Rule, R, false>());
@@ -969,7 +996,7 @@ int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals,
 }
 
 // pass 2 over the element row blocks (addressed in 16-byte units with 32-bit offsets)
-int launch_rows_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s) {
+int launch_rows_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const MassTerm& mt) {
   const bool want_f = f != nullptr, want_k = vals != nullptr;
   if (m.n_elem * m.n_pn * (int64_t)(kRowBlk / 4) >= ((int64_t)1 << 32)) return TLFEA_ERR_TOO_LARGE;
   GatherArgs g{};
@@ -980,6 +1007,9 @@ int launch_rows_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStr
   g.stage = m.d_stage;
   g.f = f;
   g.vals = vals;
+  g.mass = mt.mass;
+  g.adj_off = m.d_adj_off;
+  g.inv_h = mt.inv_h;
   g.inc_cap = (int)((m.max_range_inc + 15) / 16 * 16);
   const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows) + g.inc_cap;
   const dim3 grid((unsigned)m.n_ranges), blk(64 * m.tune.waves);
@@ -1008,8 +1038,8 @@ int launch_points_prec(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t
 }
 
 template <typename R>
-int launch_nodes_prec(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s) {
-  if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, R>(m, m.d_stage, f, vals, accum, s);
+int launch_nodes_prec(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const MassTerm& mt) {
+  if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, R>(m, m.d_stage, f, vals, accum, s, mt);
   if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, R>(m, m.d_stage, f, vals, accum, s);
   return launch_nodes_rule<RuleAncf<4, 4, 3>, R>(m, m.d_stage, f, vals, accum, s);
 }
@@ -1077,15 +1107,16 @@ int launch_points(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s) {
   return launch_points_prec<double>(m, a, want_k, s);
 }
 
-int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s) {
+int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const MassTerm& mt) {
+  if (mt.mass && (m.elem_type != TLFEA_T10 || !vals)) return TLFEA_ERR_INVALID;
   if (m.n_ranges == 0) {  // no nodes: only the (empty) outputs to clear
     if (accum) return TLFEA_OK;
     int rc = f ? launch_zero(f, m.n_dof, s) : TLFEA_OK;
     return (rc || !vals) ? rc : launch_zero(vals, m.nnz, s);
   }
-  if (m.staged == 3) return launch_rows_nodes(m, f, vals, accum, s);
-  if (m.precision == TLFEA_MIXED) return launch_nodes_prec<float>(m, f, vals, accum, s);
-  return launch_nodes_prec<double>(m, f, vals, accum, s);
+  if (m.staged == 3) return launch_rows_nodes(m, f, vals, accum, s, mt);
+  if (m.precision == TLFEA_MIXED) return launch_nodes_prec<float>(m, f, vals, accum, s, mt);
+  return launch_nodes_prec<double>(m, f, vals, accum, s, mt);
 }
 
 int launch_force_gather_f64(const Mesh& m, const double* records, double* out, hipStream_t s) {

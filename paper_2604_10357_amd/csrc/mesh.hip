@@ -125,6 +125,7 @@ void free_mesh(Mesh& m) {
   (void)hipFree(m.d_ranges);
   (void)hipFree(m.d_incpos);
   (void)hipFree(m.d_rank_inc);
+  (void)hipFree(m.d_mass);
   (void)hipFree(m.d_stage);
   m = Mesh{};
 }

@@ -359,6 +359,9 @@ int build_pattern(Mesh& m) {
   (void)hipFree(m.d_adj_off); (void)hipFree(m.d_adj); (void)hipFree(m.d_ranges);
   (void)hipFree(m.d_inc_off); (void)hipFree(m.d_inc);
   (void)hipFree(m.d_incpos); (void)hipFree(m.d_rank_inc);
+  (void)hipFree(m.d_mass);  // indexed by the old adjacency
+  m.d_mass = nullptr;
+  m.density = 0.0;
   m.d_incpos = (int32_t*)incpos.p;
   m.d_rank_inc = (uint8_t*)rank_inc.p;
   incpos.p = rank_inc.p = nullptr;

@@ -181,6 +181,8 @@ struct Mesh {
   int32_t* d_adj_off = nullptr;   // n_pnodes + 1, pattern-node adjacency
   int32_t* d_adj = nullptr;
   uint8_t* d_rank = nullptr;      // n_elem * n_pn rows of rank_stride(n_pn) bytes: rank of node b in adj(node a)
+  double* d_mass = nullptr;       // T10 consistent mass M_IJ per adjacency entry (adj_off / adj order)
+  double density = 0.0;           // of the mass above (0: not built)
   hipStream_t last_stream = nullptr;
 };
 
@@ -209,6 +211,11 @@ struct AsmArgs {
 // Pass-2 arguments of one mesh.
 struct GatherArgs {
   const int32_t* ranges;
+  // Newton matrix: M_IJ / h added to the diagonal entries of each 3x3 block
+  // (T10; mass == NULL: none)
+  const double* mass;
+  const int32_t* adj_off;
+  double inv_h;
   const int32_t* inc_off;
   const int32_t* inc;
   const int32_t* row_off;
@@ -279,7 +286,12 @@ int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tune
 int launch_zero(double* p, int64_t n, hipStream_t s);
 // pass 1: per-point records into m.d_stage; pass 2: per-node reduction into f / vals
 int launch_points(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s);
-int launch_nodes(const Mesh& m, double* f, double* vals, bool accumulate, hipStream_t s);
+struct MassTerm {
+  const double* mass = nullptr;  // per adjacency entry (Mesh::d_mass)
+  double inv_h = 0.0;
+};
+int launch_nodes(const Mesh& m, double* f, double* vals, bool accumulate, hipStream_t s,
+                 const MassTerm& mt = MassTerm{});
 
 // pattern builder (pattern.hip)
 int build_pattern(Mesh& m);

@@ -155,3 +155,7 @@ def test_argument_validation_needs_no_gpu(native):
     assert L.tlfea_batch_set_gather_shape(None, ctypes.byref(sh)) == -1
     assert L.tlfea_batch_get_gather_shape(None, ctypes.byref(sh), None) == -1
     assert L.tlfea_batch_autotune(None, None, None, None, None, None, 5, None, None, None) == -1
+    assert L.tlfea_build_mass(None, 1000.0) == -1
+    assert L.tlfea_get_mass(None, None, None) == -1
+    assert L.tlfea_assemble_newton(None, None, None, 1e-3, None, None, None) == -1
+    assert L.tlfea_newton_gradient(None, None, None, None, None, 1e-3, None, None) == -1

@@ -269,6 +269,24 @@ def bench_mesh(args, torch, wl, wname):
                                 f"k_stage_tile + k_gather ({kname}, f + K)"), "kernel_ms": ms,
                      "pass1_stage_ms": ms1, "pass2_gather_ms": ms2, "algorithmic_bytes": B},
     }
+    if wl.mesh.elem_type == 1:
+        # Newton step pieces on the same mesh: H = M/h + h K_t (one call, the
+        # mass term inside pass 2) and the gradient M (v - v_prev)/h + f_int
+        mesh.build_mass(1000.0)
+        fn = torch.empty_like(f)
+        hn = torch.empty_like(vals)
+        g = torch.empty_like(f)
+        vp = torch.zeros_like(qd)
+        mesh.assemble_newton(q, qd, h, fn, hn)
+        ms_newton = time_calls(lambda: mesh.assemble_newton(q, qd, h, fn, hn), args.steps, torch)
+        mesh.newton_gradient(qd, vp, fn, None, h, g)
+        ms_grad = time_calls(lambda: mesh.newton_gradient(qd, vp, fn, None, h, g), args.steps, torch)
+        n_pairs = nnz // 9  # adjacent node pairs (one 3x3 block each)
+        grad_bytes = 12 * n_pairs + 8 * n_dof * 4  # mass + neighbour ids; v, v_prev, f_int read, g written
+        out["newton"] = {"assemble_newton_ms": ms_newton, "vs_assemble": ms_newton / ms, "gradient_ms": ms_grad,
+                         "gradient_GBs": grad_bytes / (ms_grad * 1e-3) / 1e9, "gradient_bytes": grad_bytes,
+                         "density": 1000.0}
+        print(f"[bench] newton matrix {ms_newton:.4f} ms, gradient {ms_grad:.4f} ms", file=sys.stderr, flush=True)
     ro, cols = mesh.csr_pattern(on_device=False)
     ro, cols = ro.numpy(), cols.numpy()
     if not args.no_fp64 and args.precision == "mixed":

@@ -382,17 +382,24 @@ __device__ __forceinline__ void contract_point_rt(const Slot<R, WANT_K>& s, int 
 // from M_IJ / h on the diagonal entries (d, d) of every 3x3 block (I, J) of
 // its rows (T10: one coefficient per node; the segment is zero elsewhere).
 // Runs after the segment is cleared and before any contribution is added.
+// The range's mass entries are contiguous (adjacency order), and a node's
+// first entry within the range is rowo[3 n] / 9 (each entry is one 3x3 block
+// of each of its three rows): a lane per entry finds its node by bisection.
 __device__ __forceinline__ void add_mass_term(const GatherArgs& g, int32_t I0, int nn, double* lds,
                                               const int32_t* rowo) {
   if (!g.mass) return;
-  for (int n = threadIdx.x; n < nn; n += blockDim.x) {
-    const int32_t k0 = g.adj_off[I0 + n], k1 = g.adj_off[I0 + n + 1];
-    for (int32_t k = k0; k < k1; ++k) {
-      const double v = g.mass[k] * g.inv_h;
-      const int r = k - k0;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) lds[rowo[3 * n + d] + 3 * r + d] = v;
+  const int32_t k0 = g.adj_off[I0];
+  const int n_ent = g.adj_off[I0 + nn] - k0;
+  for (int x = threadIdx.x; x < n_ent; x += blockDim.x) {
+    int lo = 0, hi = nn - 1;  // last node whose first entry is <= x
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rowo[3 * mid] / 9 <= x) lo = mid; else hi = mid - 1;
     }
+    const int r = x - rowo[3 * lo] / 9;
+    const double v = g.mass[k0 + x] * g.inv_h;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lds[rowo[3 * lo + d] + 3 * r + d] = v;
   }
 }
 

@@ -5,7 +5,7 @@
 //   Eq. hessian, without constraint terms), the mass term entering pass 2's
 //   LDS segment so that H leaves in the same single write as K;
 //   the gradient g = M (v - v_prev)/h + f_int - f_ext (Sec. 4.4.1, Eq.
-//   grad_L, without constraint terms), a lane per node over its mass row.
+//   grad_L, without constraint terms), eight lanes per node over its mass row.
 #include <cmath>
 
 #include "tlfea_internal.h"
@@ -78,24 +78,39 @@ __global__ void k_mass_values(const int32_t* adj_off, const int32_t* row_off, co
   }
 }
 
-// g = M (v - v_prev) / h + f_int - f_ext, a lane per node
-__global__ void k_gradient(const int32_t* adj_off, const int32_t* adj, const double* mass, int64_t n_nodes,
-                           const double* v, const double* vp, const double* fint, const double* fext, double inv_h,
-                           double* g) {
-  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= n_nodes) return;
+// g = M (v - v_prev) / h + f_int - f_ext: kGradLanes lanes per node split its
+// mass row (consecutive entries: coalesced loads) and sum their parts with a
+// fixed butterfly of shuffles; lanes 0, 1, 2 of the group write g_I
+constexpr int kGradLanes = 8;
+__global__ __launch_bounds__(256) void k_gradient(const int32_t* adj_off, const int32_t* adj, const double* mass,
+                                                  int64_t n_nodes, const double* v, const double* vp,
+                                                  const double* fint, const double* fext, double inv_h, double* g) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t I = t / kGradLanes;
+  const int sub = (int)(t % kGradLanes);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int32_t k = adj_off[I]; k < adj_off[I + 1]; ++k) {
-    const int64_t J = adj[k];
-    const double m = mass[k];
-    s0 += m * (v[3 * J] - vp[3 * J]);
-    s1 += m * (v[3 * J + 1] - vp[3 * J + 1]);
-    s2 += m * (v[3 * J + 2] - vp[3 * J + 2]);
+  if (I < n_nodes) {
+    for (int32_t k = adj_off[I] + sub; k < adj_off[I + 1]; k += kGradLanes) {
+      const int64_t J = adj[k];
+      const double m = mass[k];
+      s0 += m * (v[3 * J] - vp[3 * J]);
+      s1 += m * (v[3 * J + 1] - vp[3 * J + 1]);
+      s2 += m * (v[3 * J + 2] - vp[3 * J + 2]);
+    }
   }
-  const double e0 = fext ? fext[3 * I] : 0.0, e1 = fext ? fext[3 * I + 1] : 0.0, e2 = fext ? fext[3 * I + 2] : 0.0;
-  g[3 * I] = s0 * inv_h + fint[3 * I] - e0;
-  g[3 * I + 1] = s1 * inv_h + fint[3 * I + 1] - e1;
-  g[3 * I + 2] = s2 * inv_h + fint[3 * I + 2] - e2;
+  // butterfly over the group: every lane ends with the full sums (all lanes
+  // take part; groups never straddle a wave)
+#pragma unroll
+  for (int o = kGradLanes / 2; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o, kGradLanes);
+    s1 += __shfl_xor(s1, o, kGradLanes);
+    s2 += __shfl_xor(s2, o, kGradLanes);
+  }
+  if (I < n_nodes && sub < 3) {
+    const double s = sub == 0 ? s0 : sub == 1 ? s1 : s2;
+    const int64_t r = 3 * I + sub;
+    g[r] = s * inv_h + fint[r] - (fext ? fext[r] : 0.0);
+  }
 }
 
 int blocks_of(int64_t n, int b) { return (int)((n + b - 1) / b); }
@@ -160,7 +175,7 @@ TLFEA_API int tlfea_newton_gradient(tlfea_mesh_t mesh, const double* d_v, const 
   if (!d_v || !d_v_prev || !d_f_int || !d_g || !(h > 0.0) || !std::isfinite(h)) return TLFEA_ERR_INVALID;
   Mesh& m = mesh->m;
   if (m.n_pnodes > 0)
-    hipLaunchKernelGGL(tlfea::k_gradient, dim3(tlfea::blocks_of(m.n_pnodes, 256)), dim3(256), 0,
+    hipLaunchKernelGGL(tlfea::k_gradient, dim3(tlfea::blocks_of(m.n_pnodes * tlfea::kGradLanes, 256)), dim3(256), 0,
                        (hipStream_t)stream, m.d_adj_off, m.d_adj, m.d_mass, m.n_pnodes, d_v, d_v_prev, d_f_int,
                        d_f_ext, 1.0 / h, d_g);
   TLFEA_HIP_CHECK(hipGetLastError());

@@ -287,6 +287,15 @@ def bench_mesh(args, torch, wl, wname):
                          "gradient_GBs": grad_bytes / (ms_grad * 1e-3) / 1e9, "gradient_bytes": grad_bytes,
                          "density": 1000.0}
         print(f"[bench] newton matrix {ms_newton:.4f} ms, gradient {ms_grad:.4f} ms", file=sys.stderr, flush=True)
+    if not (wl.material.kv_eta or wl.material.kv_lambda):
+        # symmetric tangent: the upper triangle alone (half the matrix writes)
+        nnz_u = mesh.build_upper_pattern()
+        vu = torch.empty(nnz_u, dtype=torch.float64, device="cuda")
+        mesh.assemble_upper(q, qd, h, 1.0, f, vu)
+        ms_u = time_calls(lambda: mesh.assemble_upper(q, qd, h, 1.0, f, vu), args.steps, torch)
+        out["upper"] = {"ms_per_step": ms_u, "vs_full": ms_u / ms, "nnz_upper": nnz_u}
+        print(f"[bench] upper triangle {ms_u:.4f} ms", file=sys.stderr, flush=True)
+        del vu
     ro, cols = mesh.csr_pattern(on_device=False)
     ro, cols = ro.numpy(), cols.numpy()
     if not args.no_fp64 and args.precision == "mixed":

@@ -136,6 +136,18 @@ int tlfea_build_csr_pattern(tlfea_mesh_t mesh, int64_t* nnz_out);
 int tlfea_get_csr_pattern(tlfea_mesh_t mesh, int32_t* row_offsets, int32_t* col_indices,
                           int32_t on_device, void* stream);
 
+/* Upper triangle of the pattern (columns >= row: each row's suffix from its
+ * diagonal on), the storage of a symmetric matrix given to a Cholesky solver
+ * (the paper keeps the symmetric positive definite system in this form for its
+ * factorization, Sec. 4.6).  Built on the device once (synchronises); nnz_upper
+ * (may be NULL) receives its length.  A new full pattern drops it. */
+int tlfea_build_upper_pattern(tlfea_mesh_t mesh, int64_t* nnz_upper);
+/* Copy it out: row_offsets[n_dof + 1], col_indices[nnz_upper]; destination
+ * semantics as in tlfea_get_csr_pattern.  TLFEA_ERR_INVALID before
+ * tlfea_build_upper_pattern. */
+int tlfea_get_csr_pattern_upper(tlfea_mesh_t mesh, int32_t* row_offsets, int32_t* col_indices,
+                                int32_t on_device, void* stream);
+
 /* Export the canonical DOF-level slot map for elements [elem_begin,
  * elem_begin + elem_count): slots[e][3a+i][3b+k] is the CSR position that
  * receives entry (i, k) of block (a, b) of element e, (3 n_en)^2 int32 per
@@ -174,6 +186,16 @@ int tlfea_assemble_ex(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot
  * Eq. hessian), without a separate clearing pass. */
 int tlfea_assemble_accumulate(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double alpha,
                               double beta, double* d_f, double* d_vals, void* stream);
+
+/* Same as tlfea_assemble_ex, with the tangent written to the upper triangle
+ * only (d_vals_upper: nnz_upper values on the pattern of
+ * tlfea_build_upper_pattern).  Only for materials without Kelvin-Voigt
+ * damping, whose tangent is symmetric (the hyperelastic dP/dF has major
+ * symmetry); TLFEA_ERR_UNSUPPORTED otherwise, TLFEA_ERR_INVALID before
+ * tlfea_build_upper_pattern.  Writes half the matrix values of the full call;
+ * the computation is the full one. */
+int tlfea_assemble_upper(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double alpha,
+                         double beta, double* d_f, double* d_vals_upper, void* stream);
 
 /* The two passes of every assembly call, exposed so that a caller can put
  * other work between them (e.g. pass 1 of the next mesh) or time them:

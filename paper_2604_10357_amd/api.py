@@ -172,6 +172,30 @@ class TLMesh:
                 "tlfea_internal_force_vjp")
         return gq, gqd, gp
 
+    def build_upper_pattern(self) -> int:
+        n = ctypes.c_int64()
+        N.check(N.lib().tlfea_build_upper_pattern(self._h, ctypes.byref(n)), "tlfea_build_upper_pattern")
+        self.nnz_upper = n.value
+        return n.value
+
+    def csr_pattern_upper(self):
+        """(row_offsets, col_indices) of the upper triangle, int32 host tensors."""
+        ro = torch.empty(self.n_dof + 1, dtype=torch.int32)
+        cols = torch.empty(max(self.nnz_upper, 1), dtype=torch.int32)
+        N.check(N.lib().tlfea_get_csr_pattern_upper(self._h, ctypes.c_void_p(ro.data_ptr()),
+                                                    ctypes.c_void_p(cols.data_ptr()), 0, None),
+                "tlfea_get_csr_pattern_upper")
+        return ro, cols[: self.nnz_upper]
+
+    def assemble_upper(self, q, qdot=None, alpha: float = 1.0, beta: float = 1.0, f=None, vals=None):
+        """f and the upper triangle of the (symmetric, undamped) tangent."""
+        f = torch.empty(self.n_dof, dtype=torch.float64, device=q.device) if f is None else f
+        vals = torch.empty(self.nnz_upper, dtype=torch.float64, device=q.device) if vals is None else vals
+        N.check(N.lib().tlfea_assemble_upper(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof), float(alpha),
+                                             float(beta), _ptr(f, n=self.n_dof), _ptr(vals, n=self.nnz_upper),
+                                             _stream()), "tlfea_assemble_upper")
+        return f, vals
+
     def build_mass(self, density: float):
         """Consistent mass matrix (T10, straight-sided elements), built once."""
         N.check(N.lib().tlfea_build_mass(self._h, float(density)), "tlfea_build_mass")

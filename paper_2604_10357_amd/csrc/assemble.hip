@@ -378,6 +378,34 @@ __device__ __forceinline__ void contract_point_rt(const Slot<R, WANT_K>& s, int 
   }
 }
 
+// The range's CSR values leave the LDS segment with plain coalesced stores:
+// the whole segment, or (upper-triangle output) the suffix of every row from
+// its diagonal on.  For the latter the range's upper row offsets are copied
+// into LDS (after the force rows; the launch reserves the room), and groups of
+// 16 lanes write a row each (one 128-byte line per store).  Called by every
+// lane of the workgroup.
+template <bool ACCUM>
+__device__ __forceinline__ void write_segment(const GatherArgs& g, int64_t row0, int nrow, int nseg, int64_t seg0,
+                                              double* lds, const int32_t* rowo) {
+  if (!g.row_off_u) {
+    double* out = g.vals + seg0;
+    for (int t = threadIdx.x; t < nseg; t += blockDim.x) out[t] = ACCUM ? out[t] + lds[t] : lds[t];
+    return;
+  }
+  int32_t* rowu = reinterpret_cast<int32_t*>(lds + nseg + nrow);
+  const int32_t u_base = g.row_off_u[row0];
+  for (int rr = threadIdx.x; rr <= nrow; rr += blockDim.x) rowu[rr] = g.row_off_u[row0 + rr] - u_base;
+  __syncthreads();
+  double* out = g.vals + u_base;
+  constexpr int GL = 16;  // lanes per row
+  const int sub = threadIdx.x % GL, groups = blockDim.x / GL;
+  for (int rr = threadIdx.x / GL; rr < nrow; rr += groups) {
+    const int u0 = rowu[rr], n = rowu[rr + 1] - u0;
+    const int beg = (rr + 1 < nrow ? rowo[rr + 1] : nseg) - n;
+    for (int j = sub; j < n; j += GL) out[u0 + j] = ACCUM ? out[u0 + j] + lds[beg + j] : lds[beg + j];
+  }
+}
+
 // Newton matrix (Sec. 4.4.2, Eq. hessian): the LDS segment of a range starts
 // from M_IJ / h on the diagonal entries (d, d) of every 3x3 block (I, J) of
 // its rows (T10: one coefficient per node; the segment is zero elsewhere).
@@ -625,10 +653,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
     }
   }
   __syncthreads();
-  if constexpr (WANT_K) {
-    double* out = g.vals + seg0;
-    for (int t = tid; t < nseg; t += blockDim.x) out[t] = ACCUM ? out[t] + lds[t] : lds[t];
-  }
+  if constexpr (WANT_K) write_segment<ACCUM>(g, row0, nrow, nseg, seg0, lds, rowo);
   if constexpr (WANT_F) {
     double* out = g.f + row0;
     for (int t = tid; t < nrow; t += blockDim.x) out[t] = ACCUM ? out[t] + lf[t] : lf[t];
@@ -876,10 +901,7 @@ __device__ __forceinline__ void gather_rows(const GatherArgs& g, int32_t I0, int
       if (k == 0) atomicAdd(lf + rl, (double)blk[(size_t)j * kRowBlk + 9 * kSlot + i]);
   }
   __syncthreads();
-  if constexpr (WANT_K) {
-    double* out = g.vals + seg0;
-    for (int t = tid; t < nseg; t += blockDim.x) out[t] = ACCUM ? out[t] + lds[t] : lds[t];
-  }
+  if constexpr (WANT_K) write_segment<ACCUM>(g, row0, nrow, nseg, seg0, lds, rowo);
   if constexpr (WANT_F) {
     double* out = g.f + row0;
     for (int t = tid; t < nrow; t += blockDim.x) out[t] = ACCUM ? out[t] + lf[t] : lf[t];
@@ -955,6 +977,9 @@ int launch_points_rule(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t
   return TLFEA_OK;
 }
 
+// LDS for a range's upper row offsets (upper-triangle output), 8-byte multiple
+size_t upper_table_bytes(const Mesh& m) { return 8 * (size_t)((m.max_range_rows + 2) / 2); }
+
 // pass 2 addresses records in 16-byte units with 32-bit offsets
 template <class Rule, typename R>
 bool records_addressable(int64_t n_elem, bool want_k) {
@@ -964,7 +989,7 @@ bool records_addressable(int64_t n_elem, bool want_k) {
 
 template <class Rule, typename R>
 int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals, bool accum, hipStream_t s,
-                      const MassTerm& mt = MassTerm{}) {
+                      const GatherOptions& mt) {
   const bool want_f = f != nullptr, want_k = vals != nullptr;
   if (!records_addressable<Rule, R>(m.n_elem, want_k)) return TLFEA_ERR_TOO_LARGE;
   GatherArgs g{};
@@ -981,9 +1006,11 @@ int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals,
   g.mass = mt.mass;
   g.adj_off = m.d_adj_off;
   g.inv_h = mt.inv_h;
+  g.row_off_u = mt.row_off_u;
   g.inc_cap = (int)((m.max_range_inc + 15) / 16 * 16);
   const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows) + g.inc_cap +
-                     (size_t)m.tune.waves * (want_k ? wave_buf_bytes<Rule, R, true>() : wave_buf_bytes<Rule, R, false>());
+                     (size_t)m.tune.waves * (want_k ? wave_buf_bytes<Rule, R, true>() : wave_buf_bytes<Rule, R, false>()) +
+                     (mt.row_off_u ? upper_table_bytes(m) : 0);
   const dim3 grid((unsigned)m.n_ranges), blk(64 * m.tune.waves);
 #define TLFEA_GATHER(F, K, A)                                                \
   do {                                                                       \
@@ -1003,7 +1030,7 @@ int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals,
 }
 
 // pass 2 over the element row blocks (addressed in 16-byte units with 32-bit offsets)
-int launch_rows_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const MassTerm& mt) {
+int launch_rows_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const GatherOptions& mt) {
   const bool want_f = f != nullptr, want_k = vals != nullptr;
   if (m.n_elem * m.n_pn * (int64_t)(kRowBlk / 4) >= ((int64_t)1 << 32)) return TLFEA_ERR_TOO_LARGE;
   GatherArgs g{};
@@ -1017,8 +1044,10 @@ int launch_rows_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStr
   g.mass = mt.mass;
   g.adj_off = m.d_adj_off;
   g.inv_h = mt.inv_h;
+  g.row_off_u = mt.row_off_u;
   g.inc_cap = (int)((m.max_range_inc + 15) / 16 * 16);
-  const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows) + g.inc_cap;
+  const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows) + g.inc_cap +
+                     (mt.row_off_u ? upper_table_bytes(m) : 0);
   const dim3 grid((unsigned)m.n_ranges), blk(64 * m.tune.waves);
 #define TLFEA_GATHER(F, K, A)                                              \
   do {                                                                     \
@@ -1045,10 +1074,10 @@ int launch_points_prec(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t
 }
 
 template <typename R>
-int launch_nodes_prec(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const MassTerm& mt) {
+int launch_nodes_prec(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const GatherOptions& mt) {
   if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, R>(m, m.d_stage, f, vals, accum, s, mt);
-  if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, R>(m, m.d_stage, f, vals, accum, s);
-  return launch_nodes_rule<RuleAncf<4, 4, 3>, R>(m, m.d_stage, f, vals, accum, s);
+  if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, R>(m, m.d_stage, f, vals, accum, s, mt);
+  return launch_nodes_rule<RuleAncf<4, 4, 3>, R>(m, m.d_stage, f, vals, accum, s, mt);
 }
 
 template <class Rule, typename R>
@@ -1114,12 +1143,12 @@ int launch_points(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s) {
   return launch_points_prec<double>(m, a, want_k, s);
 }
 
-int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const MassTerm& mt) {
+int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const GatherOptions& mt) {
   if (mt.mass && (m.elem_type != TLFEA_T10 || !vals)) return TLFEA_ERR_INVALID;
   if (m.n_ranges == 0) {  // no nodes: only the (empty) outputs to clear
     if (accum) return TLFEA_OK;
     int rc = f ? launch_zero(f, m.n_dof, s) : TLFEA_OK;
-    return (rc || !vals) ? rc : launch_zero(vals, m.nnz, s);
+    return (rc || !vals) ? rc : launch_zero(vals, mt.row_off_u ? m.nnz_u : m.nnz, s);
   }
   if (m.staged == 3) return launch_rows_nodes(m, f, vals, accum, s, mt);
   if (m.precision == TLFEA_MIXED) return launch_nodes_prec<float>(m, f, vals, accum, s, mt);
@@ -1128,9 +1157,10 @@ int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t
 
 int launch_force_gather_f64(const Mesh& m, const double* records, double* out, hipStream_t s) {
   if (m.n_ranges == 0) return launch_zero(out, m.n_dof, s);
-  if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, double>(m, records, out, nullptr, false, s);
-  if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, double>(m, records, out, nullptr, false, s);
-  return launch_nodes_rule<RuleAncf<4, 4, 3>, double>(m, records, out, nullptr, false, s);
+  const GatherOptions none;
+  if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, double>(m, records, out, nullptr, false, s, none);
+  if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, double>(m, records, out, nullptr, false, s, none);
+  return launch_nodes_rule<RuleAncf<4, 4, 3>, double>(m, records, out, nullptr, false, s, none);
 }
 
 int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tu, const BatchArgs& b,

@@ -126,6 +126,8 @@ void free_mesh(Mesh& m) {
   (void)hipFree(m.d_incpos);
   (void)hipFree(m.d_rank_inc);
   (void)hipFree(m.d_mass);
+  (void)hipFree(m.d_row_off_u);
+  (void)hipFree(m.d_cols_u);
   (void)hipFree(m.d_stage);
   m = Mesh{};
 }
@@ -587,3 +589,50 @@ TLFEA_API int tlfea_mesh_autotune(tlfea_mesh_t mesh, const double* d_q, const do
   if (ms_per_call) *ms_per_call = ms;
   return TLFEA_OK;
 }
+
+TLFEA_API int tlfea_build_upper_pattern(tlfea_mesh_t mesh, int64_t* nnz_upper) {
+  if (!mesh) return TLFEA_ERR_INVALID;
+  Mesh& m = mesh->m;
+  if (!m.has_pattern) return TLFEA_ERR_NO_PATTERN;
+  if (hipSetDevice(m.device) != hipSuccess) return TLFEA_ERR_HIP;
+  const int rc = tlfea::build_upper_pattern(m);
+  if (!rc && nnz_upper) *nnz_upper = m.nnz_u;
+  return rc;
+}
+
+TLFEA_API int tlfea_get_csr_pattern_upper(tlfea_mesh_t mesh, int32_t* row_offsets, int32_t* col_indices,
+                                          int32_t on_device, void* stream) {
+  if (!mesh || !row_offsets) return TLFEA_ERR_INVALID;
+  const Mesh& m = mesh->m;
+  if (!m.has_pattern) return TLFEA_ERR_NO_PATTERN;
+  if (!m.d_row_off_u) return TLFEA_ERR_INVALID;
+  if (!col_indices && m.nnz_u > 0) return TLFEA_ERR_INVALID;
+  if (hipSetDevice(m.device) != hipSuccess) return TLFEA_ERR_HIP;
+  const auto kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (on_device) {
+    TLFEA_HIP_CHECK(hipMemcpyAsync(row_offsets, m.d_row_off_u, sizeof(int32_t) * (m.n_dof + 1), kind,
+                                   (hipStream_t)stream));
+    if (m.nnz_u > 0)
+      TLFEA_HIP_CHECK(hipMemcpyAsync(col_indices, m.d_cols_u, sizeof(int32_t) * m.nnz_u, kind, (hipStream_t)stream));
+  } else {
+    TLFEA_HIP_CHECK(hipMemcpy(row_offsets, m.d_row_off_u, sizeof(int32_t) * (m.n_dof + 1), kind));
+    if (m.nnz_u > 0) TLFEA_HIP_CHECK(hipMemcpy(col_indices, m.d_cols_u, sizeof(int32_t) * m.nnz_u, kind));
+  }
+  return TLFEA_OK;
+}
+
+TLFEA_API int tlfea_assemble_upper(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double alpha,
+                                   double beta, double* d_f, double* d_vals_upper, void* stream) {
+  if (!mesh || !d_vals_upper) return TLFEA_ERR_INVALID;
+  Mesh& m = mesh->m;
+  if (!m.has_pattern) return TLFEA_ERR_NO_PATTERN;
+  if (!m.d_row_off_u) return TLFEA_ERR_INVALID;
+  // dP/dF of the hyperelastic laws is symmetric; the Kelvin-Voigt part is not
+  if (m.kv_eta != 0.0 || m.kv_lambda != 0.0) return TLFEA_ERR_UNSUPPORTED;
+  int rc = run_points(mesh, d_q, d_qdot, alpha, beta, true, stream);
+  if (rc) return rc;
+  tlfea::GatherOptions opt;
+  opt.row_off_u = m.d_row_off_u;
+  return tlfea::launch_nodes(m, d_f, d_vals_upper, false, (hipStream_t)stream, opt);
+}
+

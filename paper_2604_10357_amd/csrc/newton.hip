@@ -190,7 +190,7 @@ TLFEA_API int tlfea_assemble_newton(tlfea_mesh_t mesh, const double* d_q, const 
   // pass 1 with (alpha, beta) = (h, 1), then pass 2 with the mass term
   if ((rc = tlfea_assemble_points(mesh, d_q, d_qdot, h, 1.0, 1, stream))) return rc;
   Mesh& m = mesh->m;
-  tlfea::MassTerm mt;
+  tlfea::GatherOptions mt;
   mt.mass = m.d_mass;
   mt.inv_h = 1.0 / h;
   return tlfea::launch_nodes(m, d_f, d_vals, false, (hipStream_t)stream, mt);

@@ -122,6 +122,30 @@ __global__ void k_inc_tables(const int32_t* inc, int64_t ninc, int npn, const ui
   *reinterpret_cast<uint4*>(rank_inc + j * 16) = *reinterpret_cast<const uint4*>(rank + ea * 16);
 }
 
+// upper triangle: row r keeps its columns >= r, a suffix of the sorted row
+__global__ void k_upper_len(const int32_t* row_off, const int32_t* cols, int64_t n_dof, int32_t* len) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > n_dof) return;
+  if (r == n_dof) {
+    len[r] = 0;
+    return;
+  }
+  int32_t lo = row_off[r], hi = row_off[r + 1];  // first column >= r
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if (cols[mid] < r) lo = mid + 1; else hi = mid;
+  }
+  len[r] = row_off[r + 1] - lo;
+}
+
+__global__ void k_upper_cols(const int32_t* row_off, const int32_t* cols, const int32_t* row_off_u, int64_t n_dof,
+                             int32_t* cols_u) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_dof) return;
+  const int32_t u0 = row_off_u[r], n = row_off_u[r + 1] - u0, f0 = row_off[r + 1] - n;
+  for (int32_t j = 0; j < n; ++j) cols_u[u0 + j] = cols[f0 + j];
+}
+
 __global__ void k_node_nnz(const int32_t* nadj, int64_t n, int64_t blk, int64_t* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = blk * nadj[i];
@@ -362,6 +386,10 @@ int build_pattern(Mesh& m) {
   (void)hipFree(m.d_mass);  // indexed by the old adjacency
   m.d_mass = nullptr;
   m.density = 0.0;
+  (void)hipFree(m.d_row_off_u);
+  (void)hipFree(m.d_cols_u);
+  m.d_row_off_u = m.d_cols_u = nullptr;
+  m.nnz_u = -1;
   m.d_incpos = (int32_t*)incpos.p;
   m.d_rank_inc = (uint8_t*)rank_inc.p;
   incpos.p = rank_inc.p = nullptr;
@@ -429,6 +457,40 @@ RangePlan plan_ranges(const std::vector<int32_t>& inc_off, const std::vector<int
   }
   if (nodes > 0) close(nn);
   return p;
+}
+
+int build_upper_pattern(Mesh& m) {
+  if (!m.has_pattern) return TLFEA_ERR_NO_PATTERN;
+  if (m.d_row_off_u) return TLFEA_OK;
+  const int64_t n = m.n_dof;
+  DevBuf len;
+  int32_t* d_ro = nullptr;
+  TLFEA_HIP_CHECK(hipMalloc(&len.p, sizeof(int32_t) * (n + 1)));
+  TLFEA_HIP_CHECK(hipMalloc(&d_ro, sizeof(int32_t) * (n + 1)));
+  hipLaunchKernelGGL(k_upper_len, dim3(grid_of(n + 1, 256)), dim3(256), 0, nullptr, m.d_row_off, m.d_cols, n,
+                     (int32_t*)len.p);
+  hipError_t e0 = hipGetLastError();
+  int rc = e0 == hipSuccess ? scan_exclusive<int32_t>((int32_t*)len.p, d_ro, n + 1, nullptr) : TLFEA_ERR_HIP;
+  int32_t nnz_u = 0;
+  if (!rc && hipMemcpy(&nnz_u, d_ro + n, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) rc = TLFEA_ERR_HIP;
+  int32_t* d_cu = nullptr;
+  if (!rc && hipMalloc(&d_cu, sizeof(int32_t) * (nnz_u > 0 ? nnz_u : 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    rc = TLFEA_ERR_NOMEM;
+  }
+  if (!rc && n > 0)
+    hipLaunchKernelGGL(k_upper_cols, dim3(grid_of(n, 256)), dim3(256), 0, nullptr, m.d_row_off, m.d_cols, d_ro, n,
+                       d_cu);
+  if (!rc && (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)) rc = TLFEA_ERR_HIP;
+  if (rc) {
+    (void)hipFree(d_ro);
+    (void)hipFree(d_cu);
+    return rc;
+  }
+  m.d_row_off_u = d_ro;
+  m.d_cols_u = d_cu;
+  m.nnz_u = nnz_u;
+  return TLFEA_OK;
 }
 
 std::vector<GatherTuning> gather_candidates() {

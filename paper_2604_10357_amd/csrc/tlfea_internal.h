@@ -182,6 +182,9 @@ struct Mesh {
   int32_t* d_adj = nullptr;
   uint8_t* d_rank = nullptr;      // n_elem * n_pn rows of rank_stride(n_pn) bytes: rank of node b in adj(node a)
   double* d_mass = nullptr;       // T10 consistent mass M_IJ per adjacency entry (adj_off / adj order)
+  int32_t* d_row_off_u = nullptr; // upper-triangle CSR (columns >= row), built on request
+  int32_t* d_cols_u = nullptr;
+  int64_t nnz_u = -1;
   double density = 0.0;           // of the mass above (0: not built)
   hipStream_t last_stream = nullptr;
 };
@@ -216,6 +219,9 @@ struct GatherArgs {
   const double* mass;
   const int32_t* adj_off;
   double inv_h;
+  // upper-triangle output: vals holds the values of the upper CSR (row
+  // offsets row_off_u; a row's upper entries are the suffix of its full row)
+  const int32_t* row_off_u;
   const int32_t* inc_off;
   const int32_t* inc;
   const int32_t* row_off;
@@ -286,15 +292,20 @@ int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tune
 int launch_zero(double* p, int64_t n, hipStream_t s);
 // pass 1: per-point records into m.d_stage; pass 2: per-node reduction into f / vals
 int launch_points(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s);
-struct MassTerm {
+// Optional parts of pass 2: the Newton mass term, and output to the upper
+// triangle only (row offsets of the upper CSR; vals is then its values).
+struct GatherOptions {
   const double* mass = nullptr;  // per adjacency entry (Mesh::d_mass)
   double inv_h = 0.0;
+  const int32_t* row_off_u = nullptr;
 };
 int launch_nodes(const Mesh& m, double* f, double* vals, bool accumulate, hipStream_t s,
-                 const MassTerm& mt = MassTerm{});
+                 const GatherOptions& mt = GatherOptions{});
 
 // pattern builder (pattern.hip)
 int build_pattern(Mesh& m);
+// upper-triangle CSR of the mesh pattern (needs the pattern; synchronises)
+int build_upper_pattern(Mesh& m);
 // re-cut the mesh's node ranges for launch shape t (needs the pattern);
 // TLFEA_ERR_UNSUPPORTED if a range would not fit, leaving the mesh unchanged
 int set_gather_shape(Mesh& m, const GatherTuning& t);

@@ -338,3 +338,26 @@ def assemble_omp(mesh: Mesh, mat, q, qdot, alpha, beta, pattern):
     _chk(_lib_omp.orc_assemble_omp(ctypes.byref(mesh.s), ctypes.byref(mat), _dp(q), _dp(qd), alpha, beta, _dp(f),
                                    _ip(row_off), _ip(cols), _dp(vals)), "assemble_omp")
     return f, vals, int(_lib_omp.orc_omp_threads())
+
+
+def adamw_solve(mesh: Mesh, mat, pattern, mvals, q_n, v_n, f_ext, v0, h, lr, beta1, beta2, eps, wd, iters):
+    """The first-order inner solver of a time step (Sec. 4.5, Alg. 2) without
+    constraint terms, as a plain loop: AdamW with decoupled weight decay on
+    g(v) = M (v - v_n)/h + f_int(q_n + h v, v) - f_ext, starting from
+    g = m = s = 0; ``iters`` inner iterations, no early exit.  Returns (v, q, g)."""
+    v = np.array(v0, dtype=np.float64, copy=True)
+    n = v.shape[0]
+    g = np.zeros(n)
+    m = np.zeros(n)
+    s = np.zeros(n)
+    q = np.array(q_n, dtype=np.float64, copy=True)
+    for l in range(1, iters + 1):
+        m = beta1 * m + (1.0 - beta1) * g
+        s = beta2 * s + (1.0 - beta2) * g * g
+        m_hat = m / (1.0 - beta1 ** l)
+        s_hat = s / (1.0 - beta2 ** l)
+        v = (1.0 - lr * wd) * v - lr * m_hat / (np.sqrt(s_hat) + eps)
+        q = q_n + h * v
+        f, _ = assemble(mesh, mat, q, v, 1.0, 0.0, pattern=pattern, want_K=False)
+        g = gradient(pattern, mvals, v, v_n, f, f_ext, h)
+    return v, q, g

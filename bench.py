@@ -287,6 +287,28 @@ def bench_mesh(args, torch, wl, wname):
                          "gradient_GBs": grad_bytes / (ms_grad * 1e-3) / 1e9, "gradient_bytes": grad_bytes,
                          "density": 1000.0}
         print(f"[bench] newton matrix {ms_newton:.4f} ms, gradient {ms_grad:.4f} ms", file=sys.stderr, flush=True)
+        # the first-order inner solver: 100 AdamW iterations (f_int + gradient +
+        # update), checked every 25 (graph replays in between)
+        ms_fint = time_calls(lambda: mesh.internal_force(q, qd, fn), args.steps, torch)
+        s_ad = torch.cuda.Stream()
+        s_ad.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s_ad):
+            work = torch.empty(4 * n_dof, dtype=torch.float64, device="cuda")
+            vv = qd.clone()
+            qq = torch.empty_like(q)
+            mesh.adamw_solve(q, qd, vv, h, 1e-4, max_iters=26, check_every=25, q=qq, work=work)
+            vv.copy_(qd)
+            s_ad.synchronize()
+            t0 = time.perf_counter()
+            _, _, iters, _, _ = mesh.adamw_solve(q, qd, vv, h, 1e-4, max_iters=101, check_every=25, q=qq,
+                                                 work=work)
+            s_ad.synchronize()
+            dt = time.perf_counter() - t0
+        out["adamw"] = {"iterations": iters, "ms_per_iteration": dt * 1e3 / iters, "internal_force_ms": ms_fint,
+                        "check_every": 25}
+        print(f"[bench] adamw {dt * 1e3 / iters:.4f} ms per inner iteration (f_int alone {ms_fint:.4f} ms)",
+              file=sys.stderr, flush=True)
+        del work
     if not (wl.material.kv_eta or wl.material.kv_lambda):
         # symmetric tangent: the upper triangle alone (half the matrix writes)
         nnz_u = mesh.build_upper_pattern()

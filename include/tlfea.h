@@ -266,6 +266,33 @@ int tlfea_newton_gradient(tlfea_mesh_t mesh, const double* d_v, const double* d_
                           const double* d_f_int, const double* d_f_ext, double h, double* d_g,
                           void* stream);
 
+/* First-order inner solver of one time step (Sec. 4.5, Alg. 2, without the
+ * constraint and multiplier terms): AdamW with decoupled weight decay on
+ * g(v) = M (v - v_n)/h + f_int(q_n + h v, v) - f_ext.  Per inner iteration
+ * l = 1, 2, ...:  m = b1 m + (1 - b1) g;  s = b2 s + (1 - b2) g.g;
+ * v = (1 - lr wd) v - lr (m / (1 - b1^l)) / (sqrt(s / (1 - b2^l)) + eps);
+ * q = q_n + h v;  f_int(q, v);  g as above, starting from g = m = s = 0.
+ * The loop stops after max_iters iterations or when, at a check (after the
+ * first iteration and then every check_every iterations), ||g|| <= eps_in
+ * (1 + ||v||) or ||g|| <= eps_rel ||g_0|| (g_0: the first gradient).
+ * d_v holds the initial velocity on entry and the result on return; d_q
+ * receives q_n + h v; d_f_ext may be NULL.  d_work: 4 n_dof float64 of
+ * caller memory (moments, gradient, internal force; the gradient is left at
+ * d_work + 2 n_dof).  iters_out / gnorm_out (host, may be NULL): iterations
+ * run and the last ||g||.  Needs tlfea_build_mass; `stream` must not be the
+ * legacy default stream (the iterations between checks are captured into a
+ * HIP graph).  Synchronises at every check. */
+typedef struct {
+  double lr;           /* step size alpha */
+  double beta1, beta2; /* moment decay rates, in [0, 1) */
+  double eps;          /* > 0 */
+  double weight_decay; /* lambda_wd >= 0 */
+} tlfea_adamw_params;
+int tlfea_adamw_solve(tlfea_mesh_t mesh, const tlfea_adamw_params* params, double h, const double* d_q_n,
+                      const double* d_v_n, const double* d_f_ext, double* d_v, double* d_q, double* d_work,
+                      int32_t max_iters, int32_t check_every, double eps_in, double eps_rel,
+                      int32_t* iters_out, double* gnorm_out, void* stream);
+
 /* Read (and synchronise on the mesh's last stream) the runtime flag bits,
  * then clear them. */
 int tlfea_get_runtime_flags(tlfea_mesh_t mesh, uint32_t* flags);

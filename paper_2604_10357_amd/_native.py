@@ -30,7 +30,7 @@ EXPORTED = [
     "tlfea_mesh_set_gather_shape", "tlfea_mesh_get_gather_shape", "tlfea_mesh_autotune",
     "tlfea_batch_set_gather_shape", "tlfea_batch_get_gather_shape", "tlfea_batch_autotune",
     "tlfea_build_mass", "tlfea_get_mass", "tlfea_assemble_newton", "tlfea_newton_gradient",
-    "tlfea_build_upper_pattern", "tlfea_get_csr_pattern_upper", "tlfea_assemble_upper",
+    "tlfea_build_upper_pattern", "tlfea_get_csr_pattern_upper", "tlfea_assemble_upper", "tlfea_adamw_solve",
 ]
 
 
@@ -56,6 +56,11 @@ class GatherShape(ctypes.Structure):
 
     def as_dict(self):
         return {"waves": self.waves, "range_tasks": self.range_tasks, "range_values": self.range_values}
+
+
+class AdamwParams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("weight_decay", ctypes.c_double)]
 
 
 class TlfeaError(RuntimeError):
@@ -116,6 +121,8 @@ def lib() -> ctypes.CDLL:
         "tlfea_build_upper_pattern": ([vp, P(i64)], ctypes.c_int),
         "tlfea_get_csr_pattern_upper": ([vp, vp, vp, i32, vp], ctypes.c_int),
         "tlfea_assemble_upper": ([vp, vp, vp, dbl, dbl, vp, vp, vp], ctypes.c_int),
+        "tlfea_adamw_solve": ([vp, P(AdamwParams), dbl, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, P(i32), P(dbl),
+                               vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

@@ -196,6 +196,21 @@ class TLMesh:
                                              _stream()), "tlfea_assemble_upper")
         return f, vals
 
+    def adamw_solve(self, q_n, v_n, v, h: float, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0,
+                    f_ext=None, max_iters=100, check_every=10, eps_in=0.0, eps_rel=0.0, q=None, work=None):
+        """First-order inner solver of one time step (AdamW on the velocity); v is
+        updated in place.  Returns (v, q, iterations, last ||g||, gradient)."""
+        q = torch.empty_like(q_n) if q is None else q
+        work = torch.empty(4 * self.n_dof, dtype=torch.float64, device=q_n.device) if work is None else work
+        prm = N.AdamwParams(lr, beta1, beta2, eps, weight_decay)
+        it, gn = ctypes.c_int32(), ctypes.c_double()
+        N.check(N.lib().tlfea_adamw_solve(self._h, ctypes.byref(prm), float(h), _ptr(q_n, n=self.n_dof),
+                                          _ptr(v_n, n=self.n_dof), _ptr(f_ext, n=self.n_dof), _ptr(v, n=self.n_dof),
+                                          _ptr(q, n=self.n_dof), _ptr(work, n=4 * self.n_dof), int(max_iters),
+                                          int(check_every), float(eps_in), float(eps_rel), ctypes.byref(it),
+                                          ctypes.byref(gn), _stream()), "tlfea_adamw_solve")
+        return v, q, it.value, gn.value, work[2 * self.n_dof: 3 * self.n_dof]
+
     def build_mass(self, density: float):
         """Consistent mass matrix (T10, straight-sided elements), built once."""
         N.check(N.lib().tlfea_build_mass(self._h, float(density)), "tlfea_build_mass")

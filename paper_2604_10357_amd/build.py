@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libtlfea.so")
-SOURCES = ["mesh.hip", "pattern.hip", "assemble.hip", "vjp.hip", "batch.hip", "newton.hip"]
+SOURCES = ["mesh.hip", "pattern.hip", "assemble.hip", "vjp.hip", "batch.hip", "newton.hip", "adamw.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 CFLAGS = [

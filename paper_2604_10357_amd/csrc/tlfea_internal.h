@@ -186,6 +186,7 @@ struct Mesh {
   int32_t* d_cols_u = nullptr;
   int64_t nnz_u = -1;
   double density = 0.0;           // of the mass above (0: not built)
+  double* d_solver = nullptr;     // first-order solver: iteration counter, norm partials, norms
   hipStream_t last_stream = nullptr;
 };
 

@@ -162,3 +162,5 @@ def test_argument_validation_needs_no_gpu(native):
     assert L.tlfea_build_upper_pattern(None, None) == -1
     assert L.tlfea_get_csr_pattern_upper(None, None, None, 0, None) == -1
     assert L.tlfea_assemble_upper(None, None, None, 1.0, 0.0, None, None, None) == -1
+    assert L.tlfea_adamw_solve(None, None, 1e-3, None, None, None, None, None, None, 10, 5, 0.0, 0.0, None, None,
+                               None) == -1

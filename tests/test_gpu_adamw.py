@@ -1,0 +1,85 @@
+"""Parity of the first-order inner solver (AdamW on the time-step gradient,
+iterations between checks replayed from a HIP graph) with the oracle's plain
+loop, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2604_10357_amd import workloads as W
+from paper_2604_10357_amd._native import TlfeaError
+from tests.gpu_util import cuda, make_mesh, rel_err
+
+pytestmark = pytest.mark.gpu
+
+RHO, H = 1000.0, 1e-3
+
+
+def problem(seed=111):
+    wl = W.t10_beam(3, 2, 2, seed, "adamw", lx=0.3, ly=0.2, lz=0.2, frac=0.002)
+    rng = np.random.default_rng(seed)
+    v_n = rng.normal(0, 0.01, wl.mesh.n_dof)
+    f_ext = rng.normal(0, 5.0, wl.mesh.n_dof)
+    return wl, v_n, f_ext
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_adamw_matches_oracle(precision):
+    print(f"[gpu] adamw {precision}", flush=True)
+    wl, v_n, f_ext = problem()
+    m = make_mesh(wl, precision)
+    m.build_mass(RHO)
+    lr, b1, b2, eps, wd, iters = 2e-3, 0.9, 0.999, 1e-8, 0.01, 25
+    om = oracle.Mesh.of(wl.mesh)
+    pat = oracle.csr_pattern(om)
+    mv = oracle.mass_csr(om, RHO, pat)
+    v_ref, q_ref, g_ref = oracle.adamw_solve(om, oracle.material_of(wl.material), pat, mv, wl.q, v_n, f_ext, v_n,
+                                             H, lr, b1, b2, eps, wd, iters)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        v = cuda(v_n.copy())
+        v, q, done, gnorm, g = m.adamw_solve(cuda(wl.q), cuda(v_n), v, H, lr, b1, b2, eps, wd, f_ext=cuda(f_ext),
+                                             max_iters=iters, check_every=7)
+    s.synchronize()
+    assert done == iters
+    move = np.abs(v_ref - v_n).max()
+    ev = np.abs(v.cpu().numpy() - v_ref).max() / move
+    eg = rel_err(g.cpu().numpy(), g_ref)[0]
+    eq = rel_err(q.cpu().numpy() - wl.q, q_ref - wl.q)[0]
+    print(f"  v {ev:.2e}  g {eg:.2e}  q {eq:.2e}", flush=True)
+    tol = 1e-9 if precision == "fp64" else 1e-5
+    assert ev <= tol and eq <= tol and eg <= tol
+    assert abs(gnorm - np.linalg.norm(g_ref)) <= tol * np.linalg.norm(g_ref)
+    m.close()
+
+
+def test_adamw_stops_and_rejects():
+    print("[gpu] adamw stop / errors", flush=True)
+    wl, v_n, f_ext = problem(112)
+    m = make_mesh(wl, "mixed")
+    q_n = cuda(wl.q)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with pytest.raises(TlfeaError) as e:  # no mass yet
+            m.adamw_solve(q_n, cuda(v_n), cuda(v_n.copy()), H, 1e-3)
+        assert e.value.status == -1
+        m.build_mass(RHO)
+        # a loose tolerance stops at the first check
+        _, _, done, _, _ = m.adamw_solve(q_n, cuda(v_n), cuda(v_n.copy()), H, 1e-3, eps_in=1e10, max_iters=50)
+        assert done == 1
+        # a relative tolerance of 1 stops at the first check after the first iteration at the latest
+        _, _, done, _, _ = m.adamw_solve(q_n, cuda(v_n), cuda(v_n.copy()), H, 1e-3, eps_rel=1.0, max_iters=50,
+                                         check_every=4)
+        assert done == 1
+        _, _, done, _, _ = m.adamw_solve(q_n, cuda(v_n), cuda(v_n.copy()), H, 1e-3, max_iters=10, check_every=4)
+        assert done == 10
+        with pytest.raises(TlfeaError) as e:
+            m.adamw_solve(q_n, cuda(v_n), cuda(v_n.copy()), H, -1.0)
+        assert e.value.status == -1
+    s.synchronize()
+    with pytest.raises(TlfeaError) as e:  # the legacy default stream cannot be captured
+        m.adamw_solve(q_n, cuda(v_n), cuda(v_n.copy()), H, 1e-3)
+    assert e.value.status == -1
+    m.close()

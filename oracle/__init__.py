@@ -21,6 +21,7 @@ LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 T10 = 1
 ANCF3443 = 2
+ANCF3243 = 3
 SVK = 1
 MR = 2
 
@@ -49,7 +50,7 @@ class _Material(ctypes.Structure):
 class _Mesh(ctypes.Structure):
     _fields_ = [("elem_type", ctypes.c_int), ("n_coef", ctypes.c_int), ("n_elem", ctypes.c_int),
                 ("conn", ctypes.POINTER(ctypes.c_int)), ("X", ctypes.POINTER(ctypes.c_double)),
-                ("gl", ctypes.c_int * 3), ("thickness", ctypes.c_double)]
+                ("gl", ctypes.c_int * 3), ("thickness", ctypes.c_double), ("width", ctypes.c_double)]
 
 
 _lib = None
@@ -68,6 +69,7 @@ def lib():
         L.orc_t10_shape.argtypes = [dp, dp, dp]
         L.orc_t10_shape.restype = None
         L.orc_ancf3443_shape.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.orc_ancf3243_shape.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
         L.orc_energy_density.argtypes = [ctypes.POINTER(_Material), dp]
         L.orc_energy_density.restype = ctypes.c_double
         L.orc_pk1.argtypes = [ctypes.POINTER(_Material), dp, dp, dp]
@@ -120,19 +122,19 @@ def material_of(m) -> _Material:
 class Mesh:
     """Keeps the numpy arrays alive for the C struct."""
 
-    def __init__(self, elem_type, X, conn, gl=(0, 0, 0), thickness=0.0):
+    def __init__(self, elem_type, X, conn, gl=(0, 0, 0), thickness=0.0, width=0.0):
         self.X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 3)
         self.conn = np.ascontiguousarray(conn, dtype=np.int32)
         self.elem_type = int(elem_type)
         self.n_elem = int(self.conn.shape[0])
         self.n_coef = int(self.X.shape[0])
-        self.n_en = 10 if self.elem_type == T10 else 16
+        self.n_en = {T10: 10, ANCF3443: 16, ANCF3243: 8}[self.elem_type]
         self.s = _Mesh(self.elem_type, self.n_coef, self.n_elem, _ip(self.conn), _dp(self.X),
-                       (ctypes.c_int * 3)(*gl), float(thickness))
+                       (ctypes.c_int * 3)(*gl), float(thickness), float(width))
 
     @classmethod
     def of(cls, m):
-        return cls(m.elem_type, m.X, m.conn, m.gl, m.thickness)
+        return cls(m.elem_type, m.X, m.conn, m.gl, m.thickness, getattr(m, "width", 0.0))
 
     @property
     def n_dof(self):
@@ -209,6 +211,14 @@ def element_geometry(mesh: Mesh, e):
     g = np.zeros((mesh.n_qp, mesh.n_en, 3))
     _chk(lib().orc_element_geometry(ctypes.byref(mesh.s), int(e), _dp(dV), _dp(g)), "element_geometry")
     return dV, g
+
+
+def ancf3243_shape(xi, L, W, H):
+    S = np.zeros(8)
+    dS = np.zeros((8, 3))
+    _chk(lib().orc_ancf3243_shape(_dp(np.ascontiguousarray(xi, dtype=np.float64)), L, W, H, _dp(S), _dp(dS)),
+         "ancf3243_shape")
+    return S, dS
 
 
 def element(mesh: Mesh, mat, e, q, qdot=None, alpha=1.0, beta=0.0, want_K=True):

@@ -110,7 +110,7 @@ int orc_quadrature(int elem_type, const int gl[3], double* pts, double* w) {
     }
     return 5;
   }
-  if (elem_type == ORC_ANCF3443) {
+  if (elem_type == ORC_ANCF3443 || elem_type == ORC_ANCF3243) {
     double x0[8], w0[8], x1[8], w1[8], x2[8], w2[8];
     int n0 = orc_gauss_legendre(gl[0], x0, w0);
     int n1 = orc_gauss_legendre(gl[1], x1, w1);
@@ -496,7 +496,45 @@ void orc_tangent(const orc_material* m, const double Hd[9], const double Fdot[9]
 /* Element geometry and kinematics (Sec. 4.1; Sec. 4.3, Eq. F_assembly)        */
 /* ------------------------------------------------------------------------- */
 
-int orc_n_en(int elem_type) { return elem_type == ORC_T10 ? 10 : (elem_type == ORC_ANCF3443 ? 16 : 0); }
+int orc_n_en(int elem_type) {
+  return elem_type == ORC_T10 ? 10 : (elem_type == ORC_ANCF3443 ? 16 : (elem_type == ORC_ANCF3243 ? 8 : 0));
+}
+
+/* physical nodes per element (T10: 10, ANCF3443: 4, ANCF3243: 2) */
+static int nodes_per_elem(const orc_mesh* m) {
+  return m->elem_type == ORC_T10 ? 10 : (m->elem_type == ORC_ANCF3243 ? 2 : 4);
+}
+
+/* ANCF3243 beam (two nodes, coefficients r, r_x, r_y, r_z each): with
+ * xi = (1 + u)/2 along the axis (x = L xi), y = W v / 2, z = H w / 2,
+ *   node 0:  1 - 3 xi^2 + 2 xi^3,  L (xi - 2 xi^2 + xi^3),  y (1 - xi),  z (1 - xi)
+ *   node 1:  3 xi^2 - 2 xi^3,      L (xi^3 - xi^2),          y xi,        z xi
+ * (cubic Hermite interpolation of position and axial slope, linear
+ * interpolation of the cross-section gradients).  dS: parent gradients d/du,
+ * d/dv, d/dw. */
+int orc_ancf3243_shape(const double xi3[3], double L, double W, double H, double S[8], double dS[24]) {
+  if (!(L > 0.0) || !(W > 0.0) || !(H > 0.0)) return ORC_EINVAL;
+  const double t = 0.5 * (1.0 + xi3[0]), y = 0.5 * W * xi3[1], z = 0.5 * H * xi3[2];
+  const double dt = 0.5, dy = 0.5 * W, dz = 0.5 * H;  /* d xi/du, dy/dv, dz/dw */
+  S[0] = 1.0 - 3.0 * t * t + 2.0 * t * t * t;
+  S[1] = L * (t - 2.0 * t * t + t * t * t);
+  S[2] = y * (1.0 - t);
+  S[3] = z * (1.0 - t);
+  S[4] = 3.0 * t * t - 2.0 * t * t * t;
+  S[5] = L * (t * t * t - t * t);
+  S[6] = y * t;
+  S[7] = z * t;
+  const double dSdt[8] = {-6.0 * t + 6.0 * t * t, L * (1.0 - 4.0 * t + 3.0 * t * t), -y, -z,
+                          6.0 * t - 6.0 * t * t, L * (3.0 * t * t - 2.0 * t), y, z};
+  const double dSdy[8] = {0, 0, 1.0 - t, 0, 0, 0, t, 0};
+  const double dSdz[8] = {0, 0, 0, 1.0 - t, 0, 0, 0, t};
+  for (int a = 0; a < 8; ++a) {
+    dS[3 * a + 0] = dSdt[a] * dt;
+    dS[3 * a + 1] = dSdy[a] * dy;
+    dS[3 * a + 2] = dSdz[a] * dz;
+  }
+  return ORC_OK;
+}
 
 int orc_n_qp(const orc_mesh* mesh) {
   if (mesh->elem_type == ORC_T10) return 5;
@@ -506,7 +544,8 @@ int orc_n_qp(const orc_mesh* mesh) {
 /* global coefficient of local shape function a of element e */
 static int coef_of(const orc_mesh* mesh, int e, int a) {
   if (mesh->elem_type == ORC_T10) return mesh->conn[10 * e + a];
-  return 4 * mesh->conn[4 * e + a / 4] + a % 4;
+  const int npn = nodes_per_elem(mesh);
+  return 4 * mesh->conn[npn * e + a / 4] + a % 4;
 }
 
 /* parent gradients of all shape functions at qp; returns n_en */
@@ -515,6 +554,18 @@ static int parent_gradients(const orc_mesh* mesh, int e, const double* xi, doubl
     double N[10];
     orc_t10_shape(xi, N, dN);
     return 10;
+  }
+  if (mesh->elem_type == ORC_ANCF3243) {
+    const double* X = mesh->X;
+    int n0 = mesh->conn[2 * e], n1 = mesh->conn[2 * e + 1];
+    double L = 0;
+    for (int d = 0; d < 3; ++d) {
+      double a = X[3 * (4 * n1) + d] - X[3 * (4 * n0) + d];
+      L += a * a;
+    }
+    double S[8];
+    if (orc_ancf3243_shape(xi, sqrt(L), mesh->width, mesh->thickness, S, dN) != ORC_OK) return -1;
+    return 8;
   }
   /* element in-plane sizes from the reference positions of its corners */
   const double* X = mesh->X;
@@ -642,7 +693,7 @@ static int cmp_int(const void* a, const void* b) {
 }
 
 /* nodes shared by elements: T10 node = coefficient; ANCF physical node holds 4 */
-static int pattern_nodes_per_elem(const orc_mesh* m) { return m->elem_type == ORC_T10 ? 10 : 4; }
+static int pattern_nodes_per_elem(const orc_mesh* m) { return nodes_per_elem(m); }
 static int coefs_per_pattern_node(const orc_mesh* m) { return m->elem_type == ORC_T10 ? 1 : 4; }
 
 long long orc_csr_build(const orc_mesh* mesh, int* row_off, int* cols) {
@@ -926,6 +977,31 @@ int orc_element_mass(const orc_mesh* mesh, int e, double rho, double* m) {
               }
         m[10 * a + b] = rho * det0 * sum;
       }
+    return ORC_OK;
+  }
+  if (mesh->elem_type == ORC_ANCF3243) {
+    /* Gauss-Legendre 4 x 2 x 2: exact for the cubic x linear products */
+    double x4[4], w4[4], x2[2], w2[2];
+    orc_gauss_legendre(4, x4, w4);
+    orc_gauss_legendre(2, x2, w2);
+    const double* X = mesh->X;
+    int n0 = mesh->conn[2 * e], n1 = mesh->conn[2 * e + 1];
+    double L = 0;
+    for (int d = 0; d < 3; ++d) {
+      double a = X[3 * (4 * n1) + d] - X[3 * (4 * n0) + d];
+      L += a * a;
+    }
+    L = sqrt(L);
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int k = 0; k < 2; ++k) {
+          double xi[3] = {x4[i], x2[j], x2[k]}, S[8], dS[24], g[24], dV;
+          if (orc_ancf3243_shape(xi, L, mesh->width, mesh->thickness, S, dS) != ORC_OK) return ORC_EDEGENERATE;
+          int rc = qp_geometry(mesh, e, xi, w4[i] * w2[j] * w2[k], &dV, g);
+          if (rc != ORC_OK) return rc;
+          for (int a = 0; a < 8; ++a)
+            for (int b = 0; b < 8; ++b) m[8 * a + b] += rho * S[a] * S[b] * dV;
+        }
     return ORC_OK;
   }
   /* ANCF3443 */

@@ -31,6 +31,7 @@ extern "C" {
 
 #define ORC_T10 1
 #define ORC_ANCF3443 2
+#define ORC_ANCF3243 3
 #define ORC_SVK 1
 #define ORC_MR 2
 
@@ -47,13 +48,14 @@ typedef struct {
 } orc_material;
 
 typedef struct {
-  int elem_type;      /* ORC_T10 or ORC_ANCF3443 */
+  int elem_type;      /* ORC_T10, ORC_ANCF3443 or ORC_ANCF3243 */
   int n_coef;         /* number of coefficient vectors (rows of X) */
   int n_elem;
-  const int* conn;    /* T10: n_elem*10 node ids; ANCF: n_elem*4 physical node ids */
+  const int* conn;    /* T10: n_elem*10 node ids; ANCF3443: n_elem*4, ANCF3243: n_elem*2 physical node ids */
   const double* X;    /* n_coef*3 reference coefficients */
   int gl[3];          /* ANCF Gauss-Legendre points per parent direction */
-  double thickness;   /* ANCF shell thickness */
+  double thickness;   /* ANCF3443 shell thickness; ANCF3243 cross-section height (z) */
+  double width;       /* ANCF3243 cross-section width (y) */
 } orc_mesh;
 
 /* quadrature: returns the number of points (pts: nq*3 parent coords, w: nq) */
@@ -64,6 +66,7 @@ int orc_gauss_legendre(int n, double* x, double* w);
 void orc_t10_shape(const double xi[3], double N[10], double dN[30]);
 int orc_ancf3443_shape(const double xi[3], double lx, double ly, double H,
                        double S[16], double dS[48]);
+int orc_ancf3243_shape(const double xi[3], double L, double W, double H, double S[8], double dS[24]);
 
 /* pointwise constitutive law; Hd = F - I (displacement gradient), Fdot */
 double orc_energy_density(const orc_material* m, const double Hd[9]);

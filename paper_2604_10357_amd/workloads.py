@@ -36,6 +36,7 @@ import numpy as np
 
 T10 = 1
 ANCF3443 = 2
+ANCF3243 = 3
 SVK = 1
 MOONEY_RIVLIN = 2
 
@@ -57,7 +58,8 @@ class Mesh:
     X: np.ndarray             # (n_coef, 3) float64 reference coefficients
     conn: np.ndarray          # (n_elem, 10) T10 node ids | (n_elem, 4) ANCF physical nodes
     gl: tuple = (0, 0, 0)     # ANCF Gauss-Legendre points per parent direction
-    thickness: float = 0.0    # ANCF shell thickness
+    thickness: float = 0.0    # ANCF3443 shell thickness; ANCF3243 cross-section height (z)
+    width: float = 0.0        # ANCF3243 cross-section width (y)
 
     @property
     def n_elem(self) -> int:
@@ -219,6 +221,48 @@ def shell_plate(n: int, seed: int, name: str, amp=0.05, noise=1e-3, E=2e9, nu=0.
     qdot = np.zeros_like(q)
     w = rng.normal(0.0, 1.0, size=q.shape[0])
     mat = Material(SVK, (E, nu, 0.0))
+    return Workload(name, mesh, mat, q, qdot, w)
+
+
+def ancf3243_chain(n_elem: int, L: float = 0.2, W: float = 0.1, H: float = 0.1) -> Mesh:
+    """A straight chain of ANCF3243 beam elements along x (element e spans
+    nodes e and e+1); per node the coefficients r, r_x, r_y, r_z of the
+    reference configuration."""
+    n = n_elem + 1
+    x = L * np.arange(n)
+    X = np.zeros((4 * n, 3))
+    X[0::4, 0] = x
+    X[1::4, 0] = 1.0
+    X[2::4, 1] = 1.0
+    X[3::4, 2] = 1.0
+    conn = np.stack([np.arange(n_elem), np.arange(1, n)], axis=1).astype(np.int32)
+    return Mesh(ANCF3243, X, conn, (3, 2, 2), H, W)
+
+
+def beam_3243(n_elem: int, seed: int, name: str, amp=0.02, noise=1e-3, vel_sigma=0.05,
+              material: Optional[Material] = None) -> Workload:
+    """ANCF3243 chain (L = 0.2, W = H = 0.1) bent into z = amp sin(pi s) over
+    its length (s = x / length), with r_x, r_z following the curve, noise on
+    every coefficient and random velocities; SVK E = 7e8, nu = 0.33 by default."""
+    rng = np.random.default_rng(seed)
+    mesh = ancf3243_chain(n_elem)
+    span = 0.2 * n_elem
+    x = mesh.X[0::4, 0]
+    z = amp * np.sin(np.pi * x / span)
+    zx = amp * np.pi / span * np.cos(np.pi * x / span)
+    nrm = np.sqrt(1.0 + zx * zx)
+    cur = np.zeros_like(mesh.X)
+    cur[0::4] = np.stack([x, np.zeros_like(x), z], axis=1)
+    cur[1::4] = np.stack([np.ones_like(x), np.zeros_like(x), zx], axis=1)
+    cur[2::4] = np.stack([np.zeros_like(x), np.ones_like(x), np.zeros_like(x)], axis=1)
+    cur[3::4] = np.stack([-zx / nrm, np.zeros_like(x), 1.0 / nrm], axis=1)
+    scale = np.full_like(cur, noise)
+    scale[0::4] = noise * 0.2
+    cur = cur + rng.uniform(-1.0, 1.0, size=cur.shape) * scale
+    q = cur.ravel()
+    qdot = rng.normal(0.0, vel_sigma, size=q.shape[0])
+    w = rng.normal(0.0, 1.0, size=q.shape[0])
+    mat = material if material is not None else Material(SVK, (7e8, 0.33, 0.0))
     return Workload(name, mesh, mat, q, qdot, w)
 
 

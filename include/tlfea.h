@@ -57,6 +57,7 @@ extern "C" {
 /* element types */
 #define TLFEA_T10 1        /* 10-node quadratic tetrahedron, 5-point Keast rule (Sec. 4.3) */
 #define TLFEA_ANCF3443 2   /* 4-node ANCF shell, nodes carry r, r_x, r_y, r_z (Sec. 4.3) */
+#define TLFEA_ANCF3243 3   /* 2-node ANCF beam, nodes carry r, r_x, r_y, r_z; Gauss-Legendre 3x2x2 (Sec. 4.3) */
 
 /* materials (Sec. 4.3, Stage 1) */
 #define TLFEA_SVK 1           /* params = {E, nu, unused} */
@@ -76,21 +77,27 @@ typedef struct tlfea_mesh_s* tlfea_mesh_t;
 typedef struct tlfea_batch_s* tlfea_batch_t;
 
 typedef struct {
-  int32_t elem_type;      /* TLFEA_T10 | TLFEA_ANCF3443 */
+  int32_t elem_type;      /* TLFEA_T10 | TLFEA_ANCF3443 | TLFEA_ANCF3243 */
   int64_t n_coef;         /* number of coefficient vectors (T10: nodes; ANCF: 4 * nodes) */
   int64_t n_elem;
   const int32_t* h_conn;  /* T10: n_elem x 10 node ids, corners then edges (0,1),(1,2),(0,2),
                              (0,3),(1,3),(2,3); ANCF3443: n_elem x 4 node ids counter-clockwise
-                             from parent corner (-1,-1).  0-based. */
+                             from parent corner (-1,-1); ANCF3243: n_elem x 2 node ids, the
+                             element's parent axis running from the first to the second.
+                             0-based. */
   const double* h_X;      /* n_coef x 3 reference coefficients */
   int32_t gl[3];          /* ANCF3443 Gauss-Legendre points per parent direction: {3,3,2} or
-                             {4,4,3}; ignored for T10 */
-  double thickness;       /* ANCF3443 shell thickness H; ignored for T10 */
+                             {4,4,3}; ANCF3243: {3,2,2}; ignored for T10 */
+  double thickness;       /* ANCF3443 shell thickness H; ANCF3243 cross-section height H (along
+                             r_z); ignored for T10 */
   int32_t material;       /* TLFEA_SVK | TLFEA_MOONEY_RIVLIN */
   double params[3];       /* see the material constants above */
   double kv_eta;          /* Kelvin-Voigt: S_v = 2 eta Edot + kv_lambda tr(Edot) I, P_v = F S_v */
   double kv_lambda;       /* both 0 disables damping */
   int32_t precision;      /* TLFEA_FP64 | TLFEA_MIXED */
+  double width;           /* ANCF3243 cross-section width W (along r_y); ignored otherwise.  The
+                             beam's length L is the reference distance of its two nodes and its
+                             cross-section the rectangle W x H centred on the axis. */
 } tlfea_mesh_desc;
 
 /* Name of a status code (static string). */

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "lib", "libtlfea.so")
 TLFEA_OK = 0
 TLFEA_T10 = 1
 TLFEA_ANCF3443 = 2
+TLFEA_ANCF3243 = 3
 TLFEA_SVK = 1
 TLFEA_MOONEY_RIVLIN = 2
 TLFEA_FP64 = 0
@@ -48,6 +49,7 @@ class MeshDesc(ctypes.Structure):
         ("kv_eta", ctypes.c_double),
         ("kv_lambda", ctypes.c_double),
         ("precision", ctypes.c_int32),
+        ("width", ctypes.c_double),
     ]
 
 

@@ -46,6 +46,7 @@ class TLMesh:
         d.h_X = X.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         d.gl = (ctypes.c_int32 * 3)(*mesh.gl)
         d.thickness = mesh.thickness
+        d.width = getattr(mesh, "width", 0.0)
         d.material = material.kind
         p = list(material.params) + [0.0] * (3 - len(material.params))
         d.params = (ctypes.c_double * 3)(*p[:3])
@@ -60,7 +61,7 @@ class TLMesh:
         self.precision = precision
         self.n_dof = mesh.n_dof
         self.n_elem = mesh.n_elem
-        self.n_en = 10 if mesh.elem_type == N.TLFEA_T10 else 16
+        self.n_en = {N.TLFEA_T10: 10, N.TLFEA_ANCF3443: 16, N.TLFEA_ANCF3243: 8}[mesh.elem_type]
         self.nnz = -1
 
     # -- lifetime

@@ -1069,6 +1069,7 @@ int launch_rows_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStr
 template <typename R>
 int launch_points_prec(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s) {
   if (m.elem_type == TLFEA_T10) return launch_points_rule<RuleT10, R>(m, a, want_k, s);
+  if (m.elem_type == TLFEA_ANCF3243) return launch_points_rule<RuleBeam, R>(m, a, want_k, s);
   if (m.gl[0] == 3) return launch_points_rule<RuleAncf<3, 3, 2>, R>(m, a, want_k, s);
   return launch_points_rule<RuleAncf<4, 4, 3>, R>(m, a, want_k, s);
 }
@@ -1076,6 +1077,7 @@ int launch_points_prec(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t
 template <typename R>
 int launch_nodes_prec(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const GatherOptions& mt) {
   if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, R>(m, m.d_stage, f, vals, accum, s, mt);
+  if (m.elem_type == TLFEA_ANCF3243) return launch_nodes_rule<RuleBeam, R>(m, m.d_stage, f, vals, accum, s, mt);
   if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, R>(m, m.d_stage, f, vals, accum, s, mt);
   return launch_nodes_rule<RuleAncf<4, 4, 3>, R>(m, m.d_stage, f, vals, accum, s, mt);
 }
@@ -1159,6 +1161,8 @@ int launch_force_gather_f64(const Mesh& m, const double* records, double* out, h
   if (m.n_ranges == 0) return launch_zero(out, m.n_dof, s);
   const GatherOptions none;
   if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, double>(m, records, out, nullptr, false, s, none);
+  if (m.elem_type == TLFEA_ANCF3243)
+    return launch_nodes_rule<RuleBeam, double>(m, records, out, nullptr, false, s, none);
   if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, double>(m, records, out, nullptr, false, s, none);
   return launch_nodes_rule<RuleAncf<4, 4, 3>, double>(m, records, out, nullptr, false, s, none);
 }
@@ -1180,6 +1184,9 @@ int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tu, 
   if (elem_type == TLFEA_T10)
     return mixed ? launch_batch_rule<RuleT10, float>(tu, b, n_ranges, lds, s)
                  : launch_batch_rule<RuleT10, double>(tu, b, n_ranges, lds, s);
+  if (elem_type == TLFEA_ANCF3243)
+    return mixed ? launch_batch_rule<RuleBeam, float>(tu, b, n_ranges, lds, s)
+                 : launch_batch_rule<RuleBeam, double>(tu, b, n_ranges, lds, s);
   if (gl0 == 3)
     return mixed ? launch_batch_rule<RuleAncf<3, 3, 2>, float>(tu, b, n_ranges, lds, s)
                  : launch_batch_rule<RuleAncf<3, 3, 2>, double>(tu, b, n_ranges, lds, s);

@@ -15,10 +15,11 @@
 namespace tlfea {
 namespace {
 
-// J0 at every (element, point); ANCF element scales from the reference corners
+// J0 at every (element, point); ANCF element scales from the reference nodes
+// (shell: half edge lengths; beam: length L and half width)
 template <class Rule>
-__global__ void k_geometry(const int32_t* conn, const double* X, int64_t n_elem, double half_h, double* geo,
-                           double* escale, uint32_t* err) {
+__global__ void k_geometry(const int32_t* conn, const double* X, int64_t n_elem, double half_h, double half_w,
+                           double* geo, double* escale, uint32_t* err) {
   constexpr int NQ = Rule::NQ;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_elem * NQ) return;
@@ -26,7 +27,18 @@ __global__ void k_geometry(const int32_t* conn, const double* X, int64_t n_elem,
   const int q = (int)(t % NQ);
   const int32_t* ce = conn + e * Rule::NPN;
   double sc[4] = {1.0, 1.0, 1.0, 1.0};
-  if constexpr (Rule::MC == 4) {
+  if constexpr (Rule::MC == 4 && Rule::NPN == 2) {
+    const double* x0 = X + 3 * (4 * (int64_t)ce[0]);
+    const double* x1 = X + 3 * (4 * (int64_t)ce[1]);
+    sc[1] = sqrt((x1[0] - x0[0]) * (x1[0] - x0[0]) + (x1[1] - x0[1]) * (x1[1] - x0[1]) +
+                 (x1[2] - x0[2]) * (x1[2] - x0[2]));
+    sc[2] = half_w;
+    sc[3] = half_h;
+    if (q == 0) {
+      escale[2 * e] = sc[1];
+      escale[2 * e + 1] = sc[2];
+    }
+  } else if constexpr (Rule::MC == 4) {
     const double* x0 = X + 3 * (4 * (int64_t)ce[0]);
     const double* x1 = X + 3 * (4 * (int64_t)ce[1]);
     const double* x3 = X + 3 * (4 * (int64_t)ce[3]);
@@ -42,17 +54,28 @@ __global__ void k_geometry(const int32_t* conn, const double* X, int64_t n_elem,
       escale[2 * e + 1] = sc[2];
     }
   }
-  double J0[9];
+  // The position functions (T10: all; ANCF: the value functions) sum to one,
+  // so their gradients sum to zero and J0 may be formed from positions taken
+  // relative to the element's first node: the same J0, without the
+  // cancellation that absolute coordinates far from the origin (a long chain)
+  // would cost.
+  double J0[9], x_ref[3];
 #pragma unroll
   for (int k = 0; k < 9; ++k) J0[k] = 0.0;
+  {
+    const int64_t c0 = Rule::MC == 1 ? (int64_t)ce[0] : 4 * (int64_t)ce[0];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) x_ref[i] = X[3 * c0 + i];
+  }
   for (int a = 0; a < Rule::NEN; ++a) {
     int64_t c;
     if constexpr (Rule::MC == 1) c = ce[a]; else c = 4 * (int64_t)ce[a >> 2] + (a & 3);
     const double s = sc[a % 4];
+    const bool position = Rule::MC == 1 || (a & 3) == 0;
     const double d0 = Rule::dN_rt(q, a, 0) * s, d1 = Rule::dN_rt(q, a, 1) * s, d2 = Rule::dN_rt(q, a, 2) * s;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const double x = X[3 * c + i];
+      const double x = position ? X[3 * c + i] - x_ref[i] : X[3 * c + i];
       J0[3 * i] += x * d0;
       J0[3 * i + 1] += x * d1;
       J0[3 * i + 2] += x * d2;
@@ -183,16 +206,19 @@ int precompute_geometry(Mesh& m) {
   }
   (void)hipMemset(err, 0, sizeof(uint32_t));
   if (nrec > 0) {
-    const double hh = 0.5 * m.thickness;
+    const double hh = 0.5 * m.thickness, hw = 0.5 * m.width;
     if (m.elem_type == TLFEA_T10)
       hipLaunchKernelGGL(k_geometry<RuleT10>, dim3(grid_of(nrec, 256)), dim3(256), 0, 0, m.d_conn, m.d_X,
-                         m.n_elem, hh, full, m.d_escale, err);
+                         m.n_elem, hh, hw, full, m.d_escale, err);
+    else if (m.elem_type == TLFEA_ANCF3243)
+      hipLaunchKernelGGL(k_geometry<RuleBeam>, dim3(grid_of(nrec, 256)), dim3(256), 0, 0, m.d_conn, m.d_X,
+                         m.n_elem, hh, hw, full, m.d_escale, err);
     else if (m.gl[0] == 3)
       hipLaunchKernelGGL((k_geometry<RuleAncf<3, 3, 2>>), dim3(grid_of(nrec, 256)), dim3(256), 0, 0, m.d_conn,
-                         m.d_X, m.n_elem, hh, full, m.d_escale, err);
+                         m.d_X, m.n_elem, hh, hw, full, m.d_escale, err);
     else
       hipLaunchKernelGGL((k_geometry<RuleAncf<4, 4, 3>>), dim3(grid_of(nrec, 256)), dim3(256), 0, 0, m.d_conn,
-                         m.d_X, m.n_elem, hh, full, m.d_escale, err);
+                         m.d_X, m.n_elem, hh, hw, full, m.d_escale, err);
     hipLaunchKernelGGL(k_affine_check, dim3(grid_of(m.n_elem, 256)), dim3(256), 0, 0, full, m.n_elem, nq, err);
   }
   uint32_t h = 0;
@@ -289,6 +315,16 @@ TLFEA_API int tlfea_mesh_create(const tlfea_mesh_desc* d, tlfea_mesh_t* out) {
     m.n_en = 16; m.n_pn = 4; m.mc = 4; m.n_qp = d->gl[0] * d->gl[1] * d->gl[2];
     m.gl[0] = d->gl[0]; m.gl[1] = d->gl[1]; m.gl[2] = d->gl[2];
     m.thickness = d->thickness;
+    m.n_pnodes = d->n_coef / 4;
+  } else if (d->elem_type == TLFEA_ANCF3243) {
+    if (d->gl[0] != 3 || d->gl[1] != 2 || d->gl[2] != 2) return TLFEA_ERR_UNSUPPORTED;
+    if (d->n_coef % 4 != 0 || !(d->thickness > 0.0) || !(d->width > 0.0) || !std::isfinite(d->thickness) ||
+        !std::isfinite(d->width))
+      return TLFEA_ERR_INVALID;
+    m.n_en = 8; m.n_pn = 2; m.mc = 4; m.n_qp = 12;
+    m.gl[0] = 3; m.gl[1] = 2; m.gl[2] = 2;
+    m.thickness = d->thickness;
+    m.width = d->width;
     m.n_pnodes = d->n_coef / 4;
   } else {
     return TLFEA_ERR_UNSUPPORTED;

@@ -17,6 +17,7 @@ namespace {
 static __constant__ T10Table c_t10 = make_t10_table();
 static __constant__ AncfTable<3, 3, 2> c_a332 = make_ancf_table<3, 3, 2>();
 static __constant__ AncfTable<4, 4, 3> c_a443 = make_ancf_table<4, 4, 3>();
+static __constant__ BeamTable<3, 2, 2> c_b322 = make_beam_table<3, 2, 2>();
 
 template <int N>
 struct Int {
@@ -73,6 +74,14 @@ struct RuleAncf {
   }
   __device__ static double dN_rt(int q, int a, int m) { return ctab().dS[q][a][m]; }
   __device__ static double w_rt(int q) { return ctab().w[q]; }
+};
+
+// ANCF3243 beam, Gauss-Legendre 3 x 2 x 2 (two physical nodes of four coefficients)
+struct RuleBeam {
+  static constexpr int NEN = 8, NPN = 2, MC = 4, NQ = 12;
+  static constexpr double dN(int q, int a, int m) { return kBeam322.dS[q][a][m]; }
+  __device__ static double dN_rt(int q, int a, int m) { return c_b322.dS[q][a][m]; }
+  __device__ static double w_rt(int q) { return c_b322.w[q]; }
 };
 
 }  // namespace

@@ -121,4 +121,55 @@ constexpr AncfTable<NX, NY, NZ> make_ancf_table() {
 inline constexpr AncfTable<3, 3, 2> kAncf332 = make_ancf_table<3, 3, 2>();
 inline constexpr AncfTable<4, 4, 3> kAncf443 = make_ancf_table<4, 4, 3>();
 
+// ---------------------------------------------------------------------------
+// ANCF3243 beam: nodes 0, 1 at parent u = -1, 1 with coefficients r, r_x, r_y,
+// r_z.  With t = (1 + u)/2 along the axis and the parent cross-section
+// coordinates v, w (y = W v / 2, z = H w / 2) the functions of node 0 / node 1 are
+//   value : 1 - 3t^2 + 2t^3          / 3t^2 - 2t^3
+//   r_x   : L (t - 2t^2 + t^3)       / L (t^3 - t^2)
+//   r_y   : (W/2) v (1 - t)          / (W/2) v t
+//   r_z   : (H/2) w (1 - t)          / (H/2) w t
+// (cubic Hermite functions along the axis, cross-section gradients
+// interpolated linearly).  As for the shell, the table holds the gradients
+// without the element scales (1, L, W/2, H/2).
+// ---------------------------------------------------------------------------
+template <int NX, int NY, int NZ>
+struct BeamTable {
+  static constexpr int NQ = NX * NY * NZ;
+  double dS[NQ][8][3];  // unit-scaled parent gradients
+  double w[NQ];
+};
+
+template <int NX, int NY, int NZ>
+constexpr BeamTable<NX, NY, NZ> make_beam_table() {
+  BeamTable<NX, NY, NZ> t{};
+  int q = 0;
+  for (int i = 0; i < NX; ++i)
+    for (int j = 0; j < NY; ++j)
+      for (int k = 0; k < NZ; ++k) {
+        const double u = gl_node(NX, i), v = gl_node(NY, j), z = gl_node(NZ, k);
+        const double tt = 0.5 * (1.0 + u);
+        t.w[q] = gl_weight(NX, i) * gl_weight(NY, j) * gl_weight(NZ, k);
+        for (int a = 0; a < 8; ++a)
+          for (int m = 0; m < 3; ++m) t.dS[q][a][m] = 0.0;
+        // d/du = (1/2) d/dt
+        t.dS[q][0][0] = 0.5 * (6.0 * tt * tt - 6.0 * tt);
+        t.dS[q][1][0] = 0.5 * (1.0 - 4.0 * tt + 3.0 * tt * tt);
+        t.dS[q][2][0] = -0.5 * v;
+        t.dS[q][2][1] = 1.0 - tt;
+        t.dS[q][3][0] = -0.5 * z;
+        t.dS[q][3][2] = 1.0 - tt;
+        t.dS[q][4][0] = 0.5 * (6.0 * tt - 6.0 * tt * tt);
+        t.dS[q][5][0] = 0.5 * (3.0 * tt * tt - 2.0 * tt);
+        t.dS[q][6][0] = 0.5 * v;
+        t.dS[q][6][1] = tt;
+        t.dS[q][7][0] = 0.5 * z;
+        t.dS[q][7][2] = tt;
+        ++q;
+      }
+  return t;
+}
+
+inline constexpr BeamTable<3, 2, 2> kBeam322 = make_beam_table<3, 2, 2>();
+
 }  // namespace tlfea

@@ -134,12 +134,13 @@ struct Mesh {
   int device = 0;
   int elem_type = 0;
   int n_en = 0;        // shape functions (coefficient vectors) per element
-  int n_pn = 0;        // pattern nodes per element (T10: 10 nodes; ANCF: 4 physical nodes)
+  int n_pn = 0;        // pattern nodes per element (T10: 10 nodes; ANCF shell: 4, beam: 2 physical nodes)
   int mc = 0;          // coefficient vectors per pattern node (T10: 1; ANCF: 4)
   int n_qp = 0;
   int gl[3] = {0, 0, 0};
   int64_t n_elem = 0, n_coef = 0, n_pnodes = 0, n_dof = 0;
-  double thickness = 0.0;
+  double thickness = 0.0;  // ANCF shell thickness; beam cross-section height
+  double width = 0.0;      // beam cross-section width
   int precision = TLFEA_FP64;
   int material = 0;
   double params[3] = {0, 0, 0};
@@ -150,7 +151,7 @@ struct Mesh {
   double* d_X = nullptr;          // n_coef * 3
   double* d_geo = nullptr;        // records of {J0^-1 (9, row-major [m][J]), det J0}
   bool affine = false;            // true: one record per element; false: per (element, qp)
-  double* d_escale = nullptr;     // ANCF: per element {lx/2, ly/2}
+  double* d_escale = nullptr;     // ANCF: per element {lx/2, ly/2} (shell) or {L, W/2} (beam)
   uint32_t* d_flags = nullptr;    // runtime flags
   double* d_vjp_acc = nullptr;    // 5 partial sums of the parameter VJP
 

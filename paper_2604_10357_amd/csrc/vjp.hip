@@ -143,6 +143,7 @@ int launch_vjp(Mesh& m, const double* q, const double* qdot, const double* w, do
     TLFEA_HIP_CHECK(hipGetLastError());
   }
   if (m.elem_type == TLFEA_T10) rc = launch_vjp_stage<RuleT10>(a, w, zq, zqd, gacc, s);
+  else if (m.elem_type == TLFEA_ANCF3243) rc = launch_vjp_stage<RuleBeam>(a, w, zq, zqd, gacc, s);
   else if (m.gl[0] == 3) rc = launch_vjp_stage<RuleAncf<3, 3, 2>>(a, w, zq, zqd, gacc, s);
   else rc = launch_vjp_stage<RuleAncf<4, 4, 3>>(a, w, zq, zqd, gacc, s);
   if (rc) return rc;

@@ -49,16 +49,17 @@ def test_descriptor_layout_matches_header(native, tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stddef.h>\n#include <stdio.h>\n#include "tlfea.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(tlfea_mesh_desc),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(tlfea_mesh_desc),"
         " offsetof(tlfea_mesh_desc, n_coef), offsetof(tlfea_mesh_desc, h_conn), offsetof(tlfea_mesh_desc, gl),"
         " offsetof(tlfea_mesh_desc, thickness), offsetof(tlfea_mesh_desc, params),"
-        " offsetof(tlfea_mesh_desc, kv_lambda), offsetof(tlfea_mesh_desc, precision));return 0;}\n")
+        " offsetof(tlfea_mesh_desc, kv_lambda), offsetof(tlfea_mesh_desc, precision),"
+        " offsetof(tlfea_mesh_desc, width));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     D = native.MeshDesc
     want = [ctypes.sizeof(D), D.n_coef.offset, D.h_conn.offset, D.gl.offset, D.thickness.offset, D.params.offset,
-            D.kv_lambda.offset, D.precision.offset]
+            D.kv_lambda.offset, D.precision.offset, D.width.offset]
     assert got == want
 
 

@@ -6,9 +6,9 @@ values), Mooney-Rivlin + Kelvin-Voigt, mixed precision, one `tlfea_assemble`
 call per step (f_int and h * df/dq + df/dqdot with h = 1e-3, outputs
 overwritten).  Inputs are resident in HBM before the timed region.  The FP64
 form is timed on the same mesh for comparison.  Other workloads: `t10_box`
-(80 x 8 x 8 cells), `ancf_plate` (256 x 256 ANCF3443 shell, SVK, 3x3x2 rule)
-and `batched` (512 T10 cubes in one graph-captured launch pair, against the
-per-body loop).
+(80 x 8 x 8 cells), `ancf_plate` (256 x 256 ANCF3443 shell, SVK, 3x3x2 rule),
+`ancf_beam` (500,000-element ANCF3243 chain, SVK, 3x2x2 rule) and `batched`
+(512 T10 cubes in one graph-captured launch pair, against the per-body loop).
 
 Prints one JSON line: metric / value (elements per second, whole call),
 roofline of the hot path (algorithmic bytes / its event-timed duration against
@@ -51,7 +51,7 @@ def mesh_bytes(wl, nnz, affine=True):
     if m.elem_type == 1:  # T10
         return algorithmic_bytes(m.n_elem, m.n_dof, nnz, 10, 80 if affine else 80 * 5)
     nq = int(np.prod(m.gl))
-    return algorithmic_bytes(m.n_elem, m.n_dof, nnz, 4, 80 if affine else 80 * nq, 16)
+    return algorithmic_bytes(m.n_elem, m.n_dof, nnz, m.conn.shape[1], 80 if affine else 80 * nq, 16)
 
 
 def measured_traffic(precision, shape):
@@ -178,6 +178,7 @@ WORKLOADS = {
     "t10_beam": ("config5", "t10_beam_200x20x20_mr_kv"),
     "t10_box": ("config2", "t10_box_80x8x8_mr_kv"),
     "ancf_plate": ("config3", "ancf3443_plate_256x256_svk"),
+    "ancf_beam": ("beam_res32", "ancf3243_chain_500000_svk"),
 }
 
 
@@ -241,7 +242,7 @@ def bench_mesh(args, torch, wl, wname):
     B = mesh_bytes(wl, nnz)
     achieved = B / (ms * 1e-3) / 1e9
     traffic = measured_traffic(args.precision, tuning["gather_shape"]) if wname == "t10_beam" else None
-    kname = "T10" if wl.mesh.elem_type == 1 else "ANCF3443"
+    kname = {1: "T10", 2: "ANCF3443", 3: "ANCF3243"}[wl.mesh.elem_type]
     # T10 with the tangent in mixed precision takes the element-row kernels
     rows_path = wl.mesh.elem_type == 1 and args.precision == "mixed" and os.environ.get("TLFEA_ELEMENT_ROWS") != "0"
     mat = "mooney_rivlin" if wl.material.kind == 2 else "svk"

@@ -266,6 +266,13 @@ def beam_3243(n_elem: int, seed: int, name: str, amp=0.02, noise=1e-3, vel_sigma
     return Workload(name, mesh, mat, q, qdot, w)
 
 
+def beam_res32(seed: int = 1006) -> Workload:
+    """The paper's largest ANCF3243 scaling resolution (Sec. 5, ANCF3243 beam
+    element scaling): a 500,000-element chain, 500,001 nodes, 6,000,012 DOF,
+    L = 0.2, W = H = 0.1, SVK E = 7e8, nu = 0.33."""
+    return beam_3243(500_000, seed, "ancf3243_chain_500000_svk")
+
+
 def config3(seed: int = 1003) -> Workload:
     """65,536 ANCF3443 shell elements (256x256), SVK E=2e9 nu=0.3, GL 3x3x2."""
     return shell_plate(256, seed, "ancf3443_plate_256x256_svk")

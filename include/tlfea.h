@@ -244,17 +244,22 @@ int tlfea_internal_force_vjp(tlfea_mesh_t mesh, const double* d_q, const double*
                              void* stream);
 
 /* ---------------------------------------------------------------------------
- * Newton step pieces (T10 meshes of straight-sided elements).
+ * Newton step pieces (meshes of affine elements: straight-sided T10, flat
+ * rectangular ANCF3443 shells, straight prismatic ANCF3243 beams).
  * ------------------------------------------------------------------------- */
-/* Build the consistent mass matrix once (Sec. 4.1: m_ij = int rho N_i N_j dV
+/* Build the consistent mass matrix once (Sec. 4.1: m_ij = int rho s_i s_j dV
  * over each element, M_e = [m_ij I_3], assembled over the elements): exact
- * integrals of the quadratic shape functions, float64, kept on the device per
- * pair of adjacent nodes.  density > 0.  Needs the CSR pattern
- * (TLFEA_ERR_NO_PATTERN); TLFEA_ERR_UNSUPPORTED for ANCF meshes and for T10
- * meshes with curved elements.  Synchronises; a new pattern drops the mass. */
+ * integrals of the shape-function products (T10: quadratic x quadratic; ANCF:
+ * Gauss-Legendre 4 points along the cubic directions, 2 across), float64, kept
+ * on the device per pair of adjacent pattern nodes (ANCF: the 4 x 4 block of
+ * their coefficient pairs).  density > 0.  Needs the CSR pattern
+ * (TLFEA_ERR_NO_PATTERN); TLFEA_ERR_UNSUPPORTED for meshes with a non-affine
+ * element (curved T10, warped shell, curved beam).  Synchronises; a new
+ * pattern drops the mass. */
 int tlfea_build_mass(tlfea_mesh_t mesh, double density);
-/* M as DOF-level CSR values on the mesh pattern (nnz float64, device): row
- * 3I+d holds M_IJ at column 3J+d and 0 at the other columns of the block.
+/* M as DOF-level CSR values on the mesh pattern (nnz float64, device): the
+ * row of coefficient a, component d holds m_ab at column (b, d) and 0 at the
+ * other columns of each 3 x 3 block.
  * TLFEA_ERR_INVALID before tlfea_build_mass. */
 int tlfea_get_mass(tlfea_mesh_t mesh, double* d_vals, void* stream);
 /* f_int and the Newton matrix H = M/h + h K_t (Sec. 4.4.2, Eq. hessian,

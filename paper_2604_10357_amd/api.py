@@ -213,7 +213,7 @@ class TLMesh:
         return v, q, it.value, gn.value, work[2 * self.n_dof: 3 * self.n_dof]
 
     def build_mass(self, density: float):
-        """Consistent mass matrix (T10, straight-sided elements), built once."""
+        """Consistent mass matrix (affine elements of any type), built once."""
         N.check(N.lib().tlfea_build_mass(self._h, float(density)), "tlfea_build_mass")
 
     def mass_values(self, out=None, device="cuda"):

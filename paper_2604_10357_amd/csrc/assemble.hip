@@ -407,27 +407,36 @@ __device__ __forceinline__ void write_segment(const GatherArgs& g, int64_t row0,
 }
 
 // Newton matrix (Sec. 4.4.2, Eq. hessian): the LDS segment of a range starts
-// from M_IJ / h on the diagonal entries (d, d) of every 3x3 block (I, J) of
-// its rows (T10: one coefficient per node; the segment is zero elsewhere).
-// Runs after the segment is cleared and before any contribution is added.
-// The range's mass entries are contiguous (adjacency order), and a node's
-// first entry within the range is rowo[3 n] / 9 (each entry is one 3x3 block
-// of each of its three rows): a lane per entry finds its node by bisection.
+// from M_(I,k)(J,l) / h on the diagonal entries (d, d) of every 3x3 block
+// ((I,k), (J,l)) of its rows (MC coefficients k per node; the segment is zero
+// elsewhere).  Runs after the segment is cleared and before any contribution
+// is added.  The range's mass entries (one MC x MC block per adjacent node
+// pair) are contiguous in adjacency order, and a node's first entry within the
+// range is rowo[3 MC n] / (9 MC^2) (each entry is one 3 x 3 MC piece of each
+// of the node's 3 MC rows): a lane per entry finds its node by bisection.
+template <int MC>
 __device__ __forceinline__ void add_mass_term(const GatherArgs& g, int32_t I0, int nn, double* lds,
                                               const int32_t* rowo) {
   if (!g.mass) return;
+  constexpr int RPN = 3 * MC, PER = 9 * MC * MC;
   const int32_t k0 = g.adj_off[I0];
   const int n_ent = g.adj_off[I0 + nn] - k0;
   for (int x = threadIdx.x; x < n_ent; x += blockDim.x) {
     int lo = 0, hi = nn - 1;  // last node whose first entry is <= x
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (rowo[3 * mid] / 9 <= x) lo = mid; else hi = mid - 1;
+      if (rowo[RPN * mid] / PER <= x) lo = mid; else hi = mid - 1;
     }
-    const int r = x - rowo[3 * lo] / 9;
-    const double v = g.mass[k0 + x] * g.inv_h;
+    const int r = x - rowo[RPN * lo] / PER;
+    const double* mx = g.mass + (int64_t)MC * MC * (k0 + x);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) lds[rowo[3 * lo + d] + 3 * r + d] = v;
+    for (int k = 0; k < MC; ++k)
+#pragma unroll
+      for (int l = 0; l < MC; ++l) {
+        const double v = mx[MC * k + l] * g.inv_h;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) lds[rowo[RPN * lo + 3 * k + d] + 3 * MC * r + 3 * l + d] = v;
+      }
   }
 }
 
@@ -476,7 +485,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   // range-local node of every incidence (nodes < kMaxRangeNodes fit a byte)
   for (int n = tid; n < nn; n += blockDim.x)
     for (int j = pre[n] / TPI; j < pre[n + 1] / TPI; ++j) incn[j] = (uint8_t)n;
-  if constexpr (WANT_K && MC == 1) add_mass_term(g, I0, nn, lds, rowo);
+  if constexpr (WANT_K) add_mass_term<MC>(g, I0, nn, lds, rowo);
   __syncthreads();
   const int ntask = pre[nn];
   // Tasks are ordered (node, incidence, kind, row, component): task t belongs
@@ -873,7 +882,7 @@ __device__ __forceinline__ void gather_rows(const GatherArgs& g, int32_t I0, int
   __syncthreads();
   for (int n = tid; n < nn; n += blockDim.x)
     for (int j = pre[n] / TPI; j < pre[n + 1] / TPI; ++j) incn[j] = (uint8_t)n;
-  if constexpr (WANT_K) add_mass_term(g, I0, nn, lds, rowo);
+  if constexpr (WANT_K) add_mass_term<1>(g, I0, nn, lds, rowo);
   __syncthreads();
   const int ntask = pre[nn];
   const float* blk = reinterpret_cast<const float*>(g.stage);
@@ -1146,7 +1155,7 @@ int launch_points(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s) {
 }
 
 int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const GatherOptions& mt) {
-  if (mt.mass && (m.elem_type != TLFEA_T10 || !vals)) return TLFEA_ERR_INVALID;
+  if (mt.mass && !vals) return TLFEA_ERR_INVALID;
   if (m.n_ranges == 0) {  // no nodes: only the (empty) outputs to clear
     if (accum) return TLFEA_OK;
     int rc = f ? launch_zero(f, m.n_dof, s) : TLFEA_OK;

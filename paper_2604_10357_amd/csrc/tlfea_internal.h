@@ -182,7 +182,7 @@ struct Mesh {
   int32_t* d_adj_off = nullptr;   // n_pnodes + 1, pattern-node adjacency
   int32_t* d_adj = nullptr;
   uint8_t* d_rank = nullptr;      // n_elem * n_pn rows of rank_stride(n_pn) bytes: rank of node b in adj(node a)
-  double* d_mass = nullptr;       // T10 consistent mass M_IJ per adjacency entry (adj_off / adj order)
+  double* d_mass = nullptr;       // consistent mass: mc x mc block M_(I,k)(J,l) per adjacency entry (adj order)
   int32_t* d_row_off_u = nullptr; // upper-triangle CSR (columns >= row), built on request
   int32_t* d_cols_u = nullptr;
   int64_t nnz_u = -1;
@@ -297,7 +297,7 @@ int launch_points(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s);
 // Optional parts of pass 2: the Newton mass term, and output to the upper
 // triangle only (row offsets of the upper CSR; vals is then its values).
 struct GatherOptions {
-  const double* mass = nullptr;  // per adjacency entry (Mesh::d_mass)
+  const double* mass = nullptr;  // mc x mc block per adjacency entry (Mesh::d_mass)
   double inv_h = 0.0;
   const int32_t* row_off_u = nullptr;
 };

@@ -15,18 +15,22 @@ pytestmark = pytest.mark.gpu
 RHO, H = 1000.0, 1e-3
 
 
-def problem(seed=111):
-    wl = W.t10_beam(3, 2, 2, seed, "adamw", lx=0.3, ly=0.2, lz=0.2, frac=0.002)
+def problem(seed=111, kind="t10"):
+    if kind == "t10":
+        wl = W.t10_beam(3, 2, 2, seed, "adamw", lx=0.3, ly=0.2, lz=0.2, frac=0.002)
+    else:  # ANCF3243 chain
+        wl = W.beam_3243(9, seed, "adamw_beam")
     rng = np.random.default_rng(seed)
     v_n = rng.normal(0, 0.01, wl.mesh.n_dof)
     f_ext = rng.normal(0, 5.0, wl.mesh.n_dof)
     return wl, v_n, f_ext
 
 
+@pytest.mark.parametrize("kind", ["t10", "beam"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_adamw_matches_oracle(precision):
-    print(f"[gpu] adamw {precision}", flush=True)
-    wl, v_n, f_ext = problem()
+def test_adamw_matches_oracle(precision, kind):
+    print(f"[gpu] adamw {kind} {precision}", flush=True)
+    wl, v_n, f_ext = problem(kind=kind)
     m = make_mesh(wl, precision)
     m.build_mass(RHO)
     lr, b1, b2, eps, wd, iters = 2e-3, 0.9, 0.999, 1e-8, 0.01, 25

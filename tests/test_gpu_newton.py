@@ -1,6 +1,7 @@
 """Parity of the Newton-step pieces (consistent mass, Newton matrix
 H = M/h + h K_t, gradient g = M (v - v_prev)/h + f_int - f_ext) with the FP64
-CPU oracle, through the C ABI."""
+CPU oracle, through the C ABI, for T10, the ANCF3443 shell (both rules) and
+the ANCF3243 beam."""
 import numpy as np
 import pytest
 import torch
@@ -20,6 +21,12 @@ CASES = [
 _w = W.t10_beam(2, 2, 2, 82, "t10_ragged23", lx=0.2, ly=0.2, lz=0.2)
 _w.mesh = W.Mesh(W.T10, _w.mesh.X, _w.mesh.conn[:23].copy())
 CASES[1] = ("t10_ragged23", _w)
+_sh = W.shell_plate(3, 85, "ancf_3x3_443_kv", thickness=0.02, gl=(4, 4, 3))
+_sh.material = W.Material(W.SVK, (2e9, 0.3, 0.0), 5e3, 5e3)
+CASES += [("ancf_4x3_332", W.shell_plate(4, 86, "ancf_4x3", thickness=0.02)),
+          ("ancf_3x3_443_kv", _sh),
+          ("beam37_mr_kv", W.beam_3243(37, 87, "beam37_mr_kv",
+                                       material=W.Material(W.MOONEY_RIVLIN, (2e5, 5e4, 1e8), 1e3, 1e3)))]
 RHO = 1100.0
 
 
@@ -88,11 +95,16 @@ def test_newton_error_paths():
         m.assemble_newton(q, q, 0.0)
     assert e.value.status == -1
     m.close()
-    sh = make_mesh(W.shell_plate(3, 84, "ancf", thickness=0.02), "mixed")
+    # a curved beam element (a reference slope off the chord) is not supported
+    bw = W.beam_3243(2, 84, "curved_beam")
+    Xb = bw.mesh.X.copy()
+    Xb[5] = [0.995, 0.0, 0.0998]
+    cb = make_mesh(W.Workload("curved_beam", W.Mesh(W.ANCF3243, Xb, bw.mesh.conn, (3, 2, 2), 0.1, 0.1),
+                              bw.material, bw.q, bw.qdot, bw.w), "mixed")
     with pytest.raises(TlfeaError) as e:
-        sh.build_mass(RHO)
+        cb.build_mass(RHO)
     assert e.value.status == -2
-    sh.close()
+    cb.close()
     # a curved T10 element (an edge node off its edge) is not supported
     X = wl.mesh.X.copy()
     X[int(wl.mesh.conn[0, 4])] += 0.002

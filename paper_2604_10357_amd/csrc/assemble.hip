@@ -945,9 +945,125 @@ __global__ __launch_bounds__(512) void k_gather_rows_batch(BatchArgs b) {
 }
 
 // ---------------------------------------------------------------------------
+// internal force alone (every element type)
+// ---------------------------------------------------------------------------
+// Pass 1 keeps each element's points in one workgroup: a lane per point forms
+// Phat = dV P J0^-T (Sec. 4.3, Stage 1) into LDS, then a lane per (element,
+// coefficient a) sums f_a = sum_q Phat_q dN_a(q) s_a over the element's points
+// (Eq. fint_local, in the record precision) and writes the three values to the
+// node-sorted incidence position of (element, node of a), 3 MC values per
+// incidence.  Pass 2 adds each pattern node's incidence blocks in a fixed order,
+// a lane per row of f, in float64: no atomics, the same sums on every call.
+constexpr int kForceThreads = 256;
+template <class Rule>
+constexpr int force_elems() { return kForceThreads / Rule::NQ; }
+
+template <class Rule, typename R>
+__global__ __launch_bounds__(kForceThreads) void k_elem_force(AsmArgs a, const int32_t* __restrict__ incpos,
+                                                             R* __restrict__ blocks) {
+  constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN, MC = Rule::MC, EB = force_elems<Rule>();
+  constexpr size_t NOD = (size_t)EB * NEN * 6 * sizeof(double), PH = (size_t)EB * NQ * 9 * sizeof(R);
+  __shared__ __align__(16) unsigned char smem[NOD > PH ? NOD : PH];
+  __shared__ R dn[NQ * NEN * 3];  // unit-scaled parent gradients, dN_a(q)_m at 3 (NEN q + a) + m
+  const int tid = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * EB;
+  const int ne = (int)(a.n_elem - e0 < EB ? a.n_elem - e0 : EB);
+  double* nod = reinterpret_cast<double*>(smem);
+  gather_nodal<Rule>(a, e0, ne, nod);
+  for (int idx = tid; idx < NQ * NEN * 3; idx += kForceThreads) {
+    const int q = idx / (3 * NEN), r = idx - 3 * NEN * q;
+    dn[idx] = (R)Rule::dN_rt(q, r / 3, r % 3);
+  }
+  __syncthreads();
+  const bool act = tid < ne * NQ;
+  const int pl = act ? tid : 0;  // idle lanes evaluate point 0 and store nothing
+  const int el = pl / NQ, q = pl - el * NQ;
+  double Jinv[9], det, Hd[9], Fd[9];
+  tile_kinematics<Rule>(a, nod + 6 * NEN * el, e0 + el, q, Jinv, det, Hd, Fd);
+  __syncthreads();  // the nodal values are consumed: the LDS holds Phat from here on
+  PointOut<R> o;
+  const unsigned fl = point_update<R, false>(a.mp, Hd, Fd, det * Rule::w_rt(q), a.alpha, a.beta, o);
+  if (act && fl) atomicOr(a.flags, fl);
+  HatOut<R> h;
+  to_parent<R, false>(o, Jinv, h);
+  R* ph = reinterpret_cast<R*>(smem);
+  if (act) {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) ph[9 * pl + t] = h.P[t];
+  }
+  __syncthreads();
+  for (int t = tid; t < ne * NEN; t += kForceThreads) {
+    const int le = t / NEN, al = t - le * NEN;
+    R f0 = R(0), f1 = R(0), f2 = R(0);
+    for (int qq = 0; qq < NQ; ++qq) {
+      const R* p = ph + 9 * (le * NQ + qq);
+      const R* d = dn + 3 * (NEN * qq + al);
+      const R d0 = d[0], d1 = d[1], d2 = d[2];
+      f0 += p[0] * d0 + p[1] * d1 + p[2] * d2;
+      f1 += p[3] * d0 + p[4] * d1 + p[5] * d2;
+      f2 += p[6] * d0 + p[7] * d1 + p[8] * d2;
+    }
+    double sc[4];
+    element_scales<Rule>(a, e0 + le, sc);
+    const R s = (R)sc[al % 4];
+    const int64_t pos = incpos[(e0 + le) * NPN + al / MC];
+    R* out = blocks + pos * (3 * MC) + 3 * (al % MC);
+    out[0] = f0 * s;
+    out[1] = f1 * s;
+    out[2] = f2 * s;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_force_sum(const int32_t* __restrict__ inc_off, const R* __restrict__ blocks,
+                                                   int64_t n_rows, int rpn, bool accum, double* __restrict__ f) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rows) return;
+  const int64_t I = r / rpn;
+  const int j = (int)(r - I * rpn);
+  double s = 0.0;
+  for (int32_t x = inc_off[I]; x < inc_off[I + 1]; ++x) s += (double)blocks[(int64_t)x * rpn + j];
+  f[r] = accum ? f[r] + s : s;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 int grid_of(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+template <class Rule, typename R>
+int launch_force_rule(const Mesh& m, const AsmArgs& a, hipStream_t s) {
+  constexpr int EB = force_elems<Rule>();
+  const int64_t blocks = (m.n_elem + EB - 1) / EB;
+  if (blocks > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
+  if (blocks > 0)
+    hipLaunchKernelGGL((k_elem_force<Rule, R>), dim3((unsigned)blocks), dim3(kForceThreads), 0, s, a, m.d_incpos,
+                       (R*)m.d_stage);
+  TLFEA_HIP_CHECK(hipGetLastError());
+  return TLFEA_OK;
+}
+
+template <typename R>
+int launch_force_prec(const Mesh& m, const AsmArgs& a, hipStream_t s) {
+  if (m.elem_type == TLFEA_T10) return launch_force_rule<RuleT10, R>(m, a, s);
+  if (m.elem_type == TLFEA_ANCF3243) return launch_force_rule<RuleBeam, R>(m, a, s);
+  if (m.gl[0] == 3) return launch_force_rule<RuleAncf<3, 3, 2>, R>(m, a, s);
+  return launch_force_rule<RuleAncf<4, 4, 3>, R>(m, a, s);
+}
+
+int launch_force_sum(const Mesh& m, double* f, bool accum, hipStream_t s) {
+  const int rpn = 3 * m.mc;
+  if (m.n_dof > 0) {
+    if (m.precision == TLFEA_MIXED)
+      hipLaunchKernelGGL(k_force_sum<float>, dim3(grid_of(m.n_dof, 256)), dim3(256), 0, s, m.d_inc_off,
+                         (const float*)m.d_stage, m.n_dof, rpn, accum, f);
+    else
+      hipLaunchKernelGGL(k_force_sum<double>, dim3(grid_of(m.n_dof, 256)), dim3(256), 0, s, m.d_inc_off,
+                         (const double*)m.d_stage, m.n_dof, rpn, accum, f);
+  }
+  TLFEA_HIP_CHECK(hipGetLastError());
+  return TLFEA_OK;
+}
 
 // Dynamic LDS beyond 64 KiB has to be allowed per kernel; the largest size
 // granted so far is remembered per kernel (by address: kernels of one
@@ -1118,9 +1234,18 @@ bool use_rows(const Mesh& m, bool want_k) {
   return on && want_k && m.elem_type == TLFEA_T10 && m.precision == TLFEA_MIXED && m.d_incpos && m.d_rank_inc;
 }
 
+bool use_force_blocks(const Mesh& m, bool want_k) {
+  static const bool on = [] {
+    const char* v = std::getenv("TLFEA_FORCE_BLOCKS");
+    return !(v && v[0] == '0');
+  }();
+  return on && !want_k && m.d_incpos;
+}
+
 size_t stage_bytes(const Mesh& m, bool want_k) {
   if (use_rows(m, want_k)) return (size_t)m.n_elem * m.n_pn * kRowBlk * sizeof(float);
   const size_t r = m.precision == TLFEA_MIXED ? sizeof(float) : sizeof(double);
+  if (use_force_blocks(m, want_k)) return (size_t)m.n_elem * m.n_pn * 3 * m.mc * r;
   return (size_t)m.n_elem * m.n_qp * (want_k ? kRecK : kRecF) * r;
 }
 
@@ -1141,6 +1266,8 @@ int launch_zero(double* p, int64_t n, hipStream_t s) {
 }
 
 int launch_points(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s) {
+  if (use_force_blocks(m, want_k))
+    return m.precision == TLFEA_MIXED ? launch_force_prec<float>(m, a, s) : launch_force_prec<double>(m, a, s);
   if (use_rows(m, want_k)) {
     const int64_t blocks = (m.n_elem + kRowElems - 1) / kRowElems;
     if (blocks > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
@@ -1162,6 +1289,7 @@ int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t
     return (rc || !vals) ? rc : launch_zero(vals, mt.row_off_u ? m.nnz_u : m.nnz, s);
   }
   if (m.staged == 3) return launch_rows_nodes(m, f, vals, accum, s, mt);
+  if (m.staged == 4) return vals ? TLFEA_ERR_INVALID : launch_force_sum(m, f, accum, s);
   if (m.precision == TLFEA_MIXED) return launch_nodes_prec<float>(m, f, vals, accum, s, mt);
   return launch_nodes_prec<double>(m, f, vals, accum, s, mt);
 }

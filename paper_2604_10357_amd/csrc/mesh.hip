@@ -493,7 +493,7 @@ static int run_points(tlfea_mesh_t mesh, const double* q, const double* qdot, do
   if ((rc = tlfea::ensure_stage(m, tlfea::stage_bytes(m, want_k)))) return rc;
   tlfea::AsmArgs a = tlfea::make_args(m, q, qdot, nullptr, nullptr, alpha, beta);
   rc = tlfea::launch_points(m, a, want_k, s);
-  m.staged = rc ? 0 : (want_k ? (tlfea::use_rows(m, true) ? 3 : 2) : 1);
+  m.staged = rc ? 0 : (want_k ? (tlfea::use_rows(m, true) ? 3 : 2) : (tlfea::use_force_blocks(m, false) ? 4 : 1));
   m.staged_precision = m.precision;
   return rc;
 }
@@ -503,7 +503,8 @@ static int run_nodes(tlfea_mesh_t mesh, double* f, double* vals, bool accumulate
   if (!mesh || (!f && !vals)) return TLFEA_ERR_INVALID;
   Mesh& m = mesh->m;
   if (!m.has_pattern) return TLFEA_ERR_NO_PATTERN;
-  if (m.staged == 0 || (vals && m.staged < 2) || m.staged_precision != m.precision) return TLFEA_ERR_INVALID;
+  if (m.staged == 0 || (vals && (m.staged < 2 || m.staged > 3)) || m.staged_precision != m.precision)
+    return TLFEA_ERR_INVALID;
   if (hipSetDevice(m.device) != hipSuccess) return TLFEA_ERR_HIP;
   m.last_stream = (hipStream_t)stream;
   return tlfea::launch_nodes(m, f, vals, accumulate, (hipStream_t)stream);

@@ -109,9 +109,10 @@ __global__ void k_pack_inc(const int32_t* conn, int npn, const int32_t* inc_off,
   }
 }
 
-// For the element-row path (T10): the position of every (element, local node)
-// in the node-sorted incidence list, and that incidence's slot-map row copied
-// into incidence order (16 bytes each).
+// The position of every (element, local node) in the node-sorted incidence
+// list (element blocks of the force path and the element-row path), and for
+// the element-row path (T10, rank_inc non-null) that incidence's slot-map row
+// copied into incidence order (16 bytes each).
 __global__ void k_inc_tables(const int32_t* inc, int64_t ninc, int npn, const uint8_t* rank, int32_t* incpos,
                              uint8_t* rank_inc) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,7 +120,7 @@ __global__ void k_inc_tables(const int32_t* inc, int64_t ninc, int npn, const ui
   const int32_t v = inc[j];
   const int64_t ea = (int64_t)(v >> 4) * npn + (v & 15);
   incpos[ea] = (int32_t)j;
-  *reinterpret_cast<uint4*>(rank_inc + j * 16) = *reinterpret_cast<const uint4*>(rank + ea * 16);
+  if (rank_inc) *reinterpret_cast<uint4*>(rank_inc + j * 16) = *reinterpret_cast<const uint4*>(rank + ea * 16);
 }
 
 // upper triangle: row r keeps its columns >= r, a suffix of the sorted row
@@ -347,11 +348,14 @@ int build_pattern(Mesh& m) {
   // packed, sorted incidence for pass 2
   if (nn > 0)
     hipLaunchKernelGGL(k_pack_inc, dim3(grid_of(nn, 128)), dim3(128), 0, s, m.d_conn, npn, d_inc_off, d_inc, nn);
-  // incidence-ordered tables of the element-row path (T10 only)
+  // incidence positions (every element type) and the incidence-ordered
+  // slot-map rows of the element-row path (T10 only)
   DevBuf incpos, rank_inc;
-  if (m.elem_type == TLFEA_T10 && ninc > 0) {
+  if (ninc > 0) {
     static_assert(rank_stride(10) == 16, "T10 slot-map rows are 16 bytes");
-    if (hipMalloc(&incpos.p, sizeof(int32_t) * ninc) != hipSuccess || hipMalloc(&rank_inc.p, 16 * ninc) != hipSuccess) {
+    const bool t10 = m.elem_type == TLFEA_T10;
+    if (hipMalloc(&incpos.p, sizeof(int32_t) * ninc) != hipSuccess ||
+        (t10 && hipMalloc(&rank_inc.p, 16 * ninc) != hipSuccess)) {
       (void)hipGetLastError();
       (void)hipFree(d_row_off); (void)hipFree(d_cols); (void)hipFree(d_rank);
       (void)hipFree(d_adj_off); (void)hipFree(d_adj);

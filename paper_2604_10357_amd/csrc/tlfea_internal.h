@@ -171,7 +171,8 @@ struct Mesh {
   std::vector<int32_t> h_adj_off;
   void* d_stage = nullptr;        // pass-1 records
   size_t stage_cap = 0;
-  int staged = 0;                 // what the last pass 1 left: 0 none, 1 force records, 2 force + tangent
+  int staged = 0;                 // what the last pass 1 left: 0 none, 1 force records, 2 force + tangent,
+                                  // 3 element row blocks, 4 element force blocks
                                   // records, 3 element row blocks (force + tangent)
   int staged_precision = -1;
 
@@ -283,6 +284,9 @@ MatParams make_params(int material, const double* params, double eta, double lam
 // TLFEA_ELEMENT_ROWS=0 switches it off).  Pass 1 then leaves one row block per
 // incidence instead of per-point records.
 bool use_rows(const Mesh& m, bool want_k);
+// Force-only path (every element type; TLFEA_FORCE_BLOCKS=0 switches it off):
+// pass 1 leaves one float-or-double force block of 3 mc values per incidence.
+bool use_force_blocks(const Mesh& m, bool want_k);
 size_t stage_bytes(const Mesh& m, bool want_k);
 size_t stage_record_bytes(int precision);
 size_t row_block_bytes();  // element-row path: bytes per (element, node) row block

@@ -82,6 +82,33 @@ def test_force_and_tangent(name, wl, precision):
     m.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,wl", CASES, ids=[c[0] for c in CASES])
+def test_force_only_path(name, wl, precision):
+    """The force-only path (element force blocks, fixed-order node sums):
+    against the oracle, the same result on every call (no atomics), through the
+    split entry points with accumulation, and no tangent from its records."""
+    print(f"[gpu] force only {name} {precision}", flush=True)
+    from paper_2604_10357_amd._native import TlfeaError
+    m = make_mesh(wl, precision)
+    om = oracle.Mesh.of(wl.mesh)
+    q, qd = cuda(wl.q), cuda(wl.qdot)
+    f_ref, _ = oracle.assemble(om, oracle.material_of(wl.material), wl.q, wl.qdot, want_K=False)
+    f1 = m.internal_force(q, qd)
+    f2 = m.internal_force(q, qd)
+    assert rel_err(f1.cpu().numpy(), f_ref)[0] <= TOL[precision]
+    assert torch.equal(f1, f2)
+    base = torch.linspace(-1, 1, m.n_dof, dtype=torch.float64, device="cuda")
+    f3 = base.clone()
+    m.assemble_points(q, qd, 1.0, 0.0, want_tangent=False)
+    m.assemble_nodes(f3, None, accumulate=True)
+    assert rel_err((f3 - base).cpu().numpy(), f1.cpu().numpy())[0] <= 1e-14
+    with pytest.raises(TlfeaError) as e:
+        m.assemble_nodes(None, torch.empty(m.nnz, dtype=torch.float64, device="cuda"))
+    assert e.value.status == -1
+    m.close()
+
+
 def test_accumulate_adds_onto_existing_values():
     wl = W.config1()
     m = make_mesh(wl)
@@ -153,6 +180,13 @@ def test_config5_sampled(precision):
     fv = fh.reshape(-1, 3)
     eps = 1e-9 if precision == "fp64" else 1e-6
     assert np.abs(fv.sum(axis=0)).max() <= eps * np.abs(fv).max() * np.sqrt(len(fv))
+    # the force-only path on the same mesh: sampled rows and the same invariant
+    fo = m.internal_force(q, qd).cpu().numpy()
+    ef0 = np.abs(fo[rows] - f_ref[rows]).max() / fmax
+    print(f"  config5 {precision}: force-only sampled f {ef0:.2e}", flush=True)
+    assert ef0 <= TOL[precision]
+    fov = fo.reshape(-1, 3)
+    assert np.abs(fov.sum(axis=0)).max() <= eps * np.abs(fov).max() * np.sqrt(len(fov))
     m.close()
 
 

@@ -270,46 +270,49 @@ def bench_mesh(args, torch, wl, wname):
                                 f"k_stage_tile + k_gather ({kname}, f + K)"), "kernel_ms": ms,
                      "pass1_stage_ms": ms1, "pass2_gather_ms": ms2, "algorithmic_bytes": B},
     }
-    if wl.mesh.elem_type == 1:
-        # Newton step pieces on the same mesh: H = M/h + h K_t (one call, the
-        # mass term inside pass 2) and the gradient M (v - v_prev)/h + f_int
-        mesh.build_mass(1000.0)
-        fn = torch.empty_like(f)
-        hn = torch.empty_like(vals)
-        g = torch.empty_like(f)
-        vp = torch.zeros_like(qd)
-        mesh.assemble_newton(q, qd, h, fn, hn)
-        ms_newton = time_calls(lambda: mesh.assemble_newton(q, qd, h, fn, hn), args.steps, torch)
-        mesh.newton_gradient(qd, vp, fn, None, h, g)
-        ms_grad = time_calls(lambda: mesh.newton_gradient(qd, vp, fn, None, h, g), args.steps, torch)
-        n_pairs = nnz // 9  # adjacent node pairs (one 3x3 block each)
-        grad_bytes = 12 * n_pairs + 8 * n_dof * 4  # mass + neighbour ids; v, v_prev, f_int read, g written
-        out["newton"] = {"assemble_newton_ms": ms_newton, "vs_assemble": ms_newton / ms, "gradient_ms": ms_grad,
-                         "gradient_GBs": grad_bytes / (ms_grad * 1e-3) / 1e9, "gradient_bytes": grad_bytes,
-                         "density": 1000.0}
-        print(f"[bench] newton matrix {ms_newton:.4f} ms, gradient {ms_grad:.4f} ms", file=sys.stderr, flush=True)
-        # the first-order inner solver: 100 AdamW iterations (f_int + gradient +
-        # update), checked every 25 (graph replays in between)
-        ms_fint = time_calls(lambda: mesh.internal_force(q, qd, fn), args.steps, torch)
-        s_ad = torch.cuda.Stream()
-        s_ad.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s_ad):
-            work = torch.empty(4 * n_dof, dtype=torch.float64, device="cuda")
-            vv = qd.clone()
-            qq = torch.empty_like(q)
-            mesh.adamw_solve(q, qd, vv, h, 1e-4, max_iters=26, check_every=25, q=qq, work=work)
-            vv.copy_(qd)
-            s_ad.synchronize()
-            t0 = time.perf_counter()
-            _, _, iters, _, _ = mesh.adamw_solve(q, qd, vv, h, 1e-4, max_iters=101, check_every=25, q=qq,
-                                                 work=work)
-            s_ad.synchronize()
-            dt = time.perf_counter() - t0
-        out["adamw"] = {"iterations": iters, "ms_per_iteration": dt * 1e3 / iters, "internal_force_ms": ms_fint,
-                        "check_every": 25}
-        print(f"[bench] adamw {dt * 1e3 / iters:.4f} ms per inner iteration (f_int alone {ms_fint:.4f} ms)",
-              file=sys.stderr, flush=True)
-        del work
+    # Newton step pieces on the same mesh: H = M/h + h K_t (one call, the
+    # mass term inside pass 2) and the gradient M (v - v_prev)/h + f_int;
+    # density: the paper's scaling benchmarks use 2700 kg/m^3
+    rho = 2700.0
+    mesh.build_mass(rho)
+    fn = torch.empty_like(f)
+    hn = torch.empty_like(vals)
+    g = torch.empty_like(f)
+    vp = torch.zeros_like(qd)
+    mesh.assemble_newton(q, qd, h, fn, hn)
+    ms_newton = time_calls(lambda: mesh.assemble_newton(q, qd, h, fn, hn), args.steps, torch)
+    mesh.newton_gradient(qd, vp, fn, None, h, g)
+    ms_grad = time_calls(lambda: mesh.newton_gradient(qd, vp, fn, None, h, g), args.steps, torch)
+    mc = 1 if wl.mesh.elem_type == 1 else 4  # coefficient vectors per node
+    n_pairs = nnz // (9 * mc * mc)  # adjacent node pairs (one 3 mc x 3 mc block each)
+    # mass blocks + neighbour ids; v, v_prev, f_int read, g written
+    grad_bytes = (8 * mc * mc + 4) * n_pairs + 8 * n_dof * 4
+    out["newton"] = {"assemble_newton_ms": ms_newton, "vs_assemble": ms_newton / ms, "gradient_ms": ms_grad,
+                     "gradient_GBs": grad_bytes / (ms_grad * 1e-3) / 1e9, "gradient_bytes": grad_bytes,
+                     "density": rho}
+    print(f"[bench] newton matrix {ms_newton:.4f} ms, gradient {ms_grad:.4f} ms", file=sys.stderr, flush=True)
+    # the first-order inner solver: 100 AdamW iterations (f_int + gradient +
+    # update), checked every 25 (graph replays in between)
+    ms_fint = time_calls(lambda: mesh.internal_force(q, qd, fn), args.steps, torch)
+    s_ad = torch.cuda.Stream()
+    s_ad.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s_ad):
+        work = torch.empty(4 * n_dof, dtype=torch.float64, device="cuda")
+        vv = qd.clone()
+        qq = torch.empty_like(q)
+        mesh.adamw_solve(q, qd, vv, h, 1e-4, max_iters=26, check_every=25, q=qq, work=work)
+        vv.copy_(qd)
+        s_ad.synchronize()
+        t0 = time.perf_counter()
+        _, _, iters, _, _ = mesh.adamw_solve(q, qd, vv, h, 1e-4, max_iters=101, check_every=25, q=qq,
+                                             work=work)
+        s_ad.synchronize()
+        dt = time.perf_counter() - t0
+    out["adamw"] = {"iterations": iters, "ms_per_iteration": dt * 1e3 / iters, "internal_force_ms": ms_fint,
+                    "check_every": 25}
+    print(f"[bench] adamw {dt * 1e3 / iters:.4f} ms per inner iteration (f_int alone {ms_fint:.4f} ms)",
+          file=sys.stderr, flush=True)
+    del work
     if not (wl.material.kv_eta or wl.material.kv_lambda):
         # symmetric tangent: the upper triangle alone (half the matrix writes)
         nnz_u = mesh.build_upper_pattern()

@@ -243,8 +243,8 @@ def bench_mesh(args, torch, wl, wname):
     achieved = B / (ms * 1e-3) / 1e9
     traffic = measured_traffic(args.precision, tuning["gather_shape"]) if wname == "t10_beam" else None
     kname = {1: "T10", 2: "ANCF3443", 3: "ANCF3243"}[wl.mesh.elem_type]
-    # T10 with the tangent in mixed precision takes the element-row kernels
-    rows_path = wl.mesh.elem_type == 1 and args.precision == "mixed" and os.environ.get("TLFEA_ELEMENT_ROWS") != "0"
+    # the tangent in mixed precision takes the element-row kernels
+    rows_path = args.precision == "mixed" and os.environ.get("TLFEA_ELEMENT_ROWS") != "0"
     mat = "mooney_rivlin" if wl.material.kind == 2 else "svk"
     if wl.material.kv_eta or wl.material.kv_lambda:
         mat += "+kelvin_voigt"
@@ -266,7 +266,8 @@ def bench_mesh(args, torch, wl, wname):
         "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": (f"k_elem_rows + k_gather_rows ({kname}, f + K)" if rows_path else
+                     "kernel": (f"k_elem_rows{'' if kname == 'T10' else '_mc'} + k_gather_rows"
+                                f"{'' if kname == 'T10' else '_mc'} ({kname}, f + K)" if rows_path else
                                 f"k_stage_tile + k_gather ({kname}, f + K)"), "kernel_ms": ms,
                      "pass1_stage_ms": ms1, "pass2_gather_ms": ms2, "algorithmic_bytes": B},
     }

@@ -945,6 +945,205 @@ __global__ __launch_bounds__(512) void k_gather_rows_batch(BatchArgs b) {
 }
 
 // ---------------------------------------------------------------------------
+// element rows for ANCF (four coefficient vectors per node; float32 tangent)
+// ---------------------------------------------------------------------------
+// The same split as for T10, for the shell and the beam: pass 1 contracts an
+// element's points itself and leaves one block per (element, node) incidence
+// at the node's place in the node-sorted incidence list; pass 2 reads every
+// block once.  Block of an incidence: for row r = 3 c + i (coefficient kind c
+// of the node, component i) and column component k, the NEN entries
+// K_e[(a, i), (b, k)] over the element's coefficients b at (3 r + k) NEN + b,
+// then the parts P^_ik dN_a,k s_a of f_a,i at 36 NEN + 3 r + k (the three
+// parts of a row are added in pass 2).
+constexpr int kRowsMcThreads = 128;
+#ifndef TLFEA_ROWS_MC_UNROLL
+#define TLFEA_ROWS_MC_UNROLL 2
+#endif
+constexpr int kRowsMcUnroll = TLFEA_ROWS_MC_UNROLL;  // points contracted per step (divides 12, 18 and 48)
+template <class Rule>
+constexpr int rows_mc_elems() { return kRowsMcThreads / Rule::NQ; }
+template <int NEN>
+constexpr int rows_mc_block() { return 36 * NEN + 36; }
+
+template <class Rule>
+__global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc(AsmArgs a, const int32_t* __restrict__ incpos,
+                                                                 float* __restrict__ rows) {
+  constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN, EB = rows_mc_elems<Rule>();
+  constexpr int BLK = rows_mc_block<NEN>();
+  static_assert(Rule::MC == 4 && NEN % 4 == 0 && EB >= 1, "element rows of four-coefficient nodes");
+  constexpr size_t NOD = (size_t)EB * NEN * 6 * sizeof(double), REC = (size_t)EB * NQ * kRecL * sizeof(float);
+  __shared__ __align__(16) unsigned char smem[NOD > REC ? NOD : REC];
+  __shared__ float dn[NQ * NEN * 3];  // unit-scaled parent gradients, dN_a(q)_m at 3 (NEN q + a) + m
+  const int tid = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * EB;
+  const int ne = (int)(a.n_elem - e0 < EB ? a.n_elem - e0 : EB);
+  double* nod = reinterpret_cast<double*>(smem);
+  gather_nodal<Rule>(a, e0, ne, nod);
+  for (int idx = tid; idx < NQ * NEN * 3; idx += kRowsMcThreads) {
+    const int q = idx / (3 * NEN), r = idx - 3 * NEN * q;
+    dn[idx] = Rule::dNf_rt(q, r / 3, r % 3);
+  }
+  __syncthreads();
+  // 1. a lane per point: kinematics, constitutive update, the point's record
+  //    (the tangent-record layout of the point-record path) into LDS
+  const bool act = tid < ne * NQ;
+  const int pl = act ? tid : 0;  // idle lanes evaluate point 0 and store nothing
+  const int el = pl / NQ, q = pl - el * NQ;
+  double Jinv[9], det, Hd[9], Fd[9];
+  tile_kinematics<Rule>(a, nod + 6 * NEN * el, e0 + el, q, Jinv, det, Hd, Fd);
+  __syncthreads();  // the nodal values are consumed: the LDS holds the records from here on
+  PointOut<float> o;
+  const unsigned fl = point_update<float, true>(a.mp, Hd, Fd, det * Rule::w_rt(q), a.alpha, a.beta, o);
+  if (act && fl) atomicOr(a.flags, fl);
+  HatOut<float> h;
+  to_parent<float, true>(o, Jinv, h);
+  float* rec = reinterpret_cast<float*>(smem);
+  if (act) {
+    float* r = rec + pl * kRecL;
+    sfor<0, kRecL / 4>([&](auto jc) __attribute__((always_inline)) {
+      constexpr int j = decltype(jc)::value;
+      f32x4 v;
+      sfor<0, 4>([&](auto xc) __attribute__((always_inline)) {
+        constexpr int x = decltype(xc)::value;
+        v[x] = record_value<4 * j + x>(h);
+      });
+      *reinterpret_cast<f32x4*>(r + 4 * j) = v;
+    });
+  }
+  __syncthreads();
+  // 2. a lane per task (element, coefficient a, row i, component k), tasks in
+  //    block order; the point loop is uniform across the workgroup, so the
+  //    gradients dN_b(q) of the columns come through the scalar cache
+  const int ntask = ne * NEN * 9;
+  for (int t0 = 0; t0 < EB * NEN * 9; t0 += kRowsMcThreads) {
+    const int t = t0 + tid;
+    const bool on = t < ntask;
+    const int tt = on ? t : ntask - 1;
+    const int le = tt / (NEN * 9), r9 = tt - le * NEN * 9, al = r9 / 9, s = r9 - 9 * al;  // s = 3 i + k
+    const int k = s % 3;
+    float acc[NEN];
+#pragma unroll
+    for (int b = 0; b < NEN; ++b) acc[b] = 0.0f;
+    float facc = 0.0f;
+    const float* recp = rec + le * NQ * kRecL + kSlot * s;
+    static_assert(NQ % kRowsMcUnroll == 0, "point steps tile the rule");
+#pragma unroll 1
+    for (int q0 = 0; q0 < NQ; q0 += kRowsMcUnroll) {
+      sfor<0, kRowsMcUnroll>([&](auto uc) __attribute__((always_inline)) {
+        const int qq = q0 + decltype(uc)::value;
+        const float* sl = recp + qq * kRecL;
+        float v[10];
+#pragma unroll
+        for (int x = 0; x < 5; ++x) {
+          const f32x2 w = *reinterpret_cast<const f32x2*>(sl + 2 * x);
+          v[2 * x] = w[0];
+          v[2 * x + 1] = w[1];
+        }
+        const float* d = dn + 3 * (NEN * qq + al);
+        const float d0 = d[0], d1 = d[1], d2 = d[2];
+        const float t0n = v[0] * d0 + v[3] * d1 + v[6] * d2;
+        const float t1n = v[1] * d0 + v[4] * d1 + v[7] * d2;
+        const float t2n = v[2] * d0 + v[5] * d1 + v[8] * d2;
+        facc += v[9] * (k == 0 ? d0 : k == 1 ? d1 : d2);
+#pragma unroll
+        for (int b = 0; b < NEN; ++b)
+          acc[b] += t0n * Rule::dNf_rt(qq, b, 0) + t1n * Rule::dNf_rt(qq, b, 1) + t2n * Rule::dNf_rt(qq, b, 2);
+      });
+    }
+    if (on) {
+      double sc[4];
+      element_scales<Rule>(a, e0 + le, sc);
+      const float s_a = (float)sc[al & 3];
+      const int64_t pos = incpos[(e0 + le) * NPN + (al >> 2)];
+      const int r = 3 * (al & 3) + s / 3;  // block row (kind, i)
+      float* blk = rows + pos * BLK;
+      f32x4* outv = reinterpret_cast<f32x4*>(blk + (3 * r + k) * NEN);
+#pragma unroll
+      for (int u = 0; u < NEN / 4; ++u) {
+        f32x4 w;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) w[x] = acc[4 * u + x] * s_a * (float)sc[x];  // b = 4 u + x: kind x
+        outv[u] = w;
+      }
+      blk[36 * NEN + 3 * r + k] = facc * s_a;
+    }
+  }
+}
+
+// Pass 2 over the ANCF row blocks: a lane per (incidence, row r, component k)
+// loads its NEN entries (16-byte pieces) and its element's rank row (4 bytes,
+// element order), and adds them into the range's LDS segment at
+// row + 3 (4 rank_b + c_b) + k; every lane adds its force part to the row.
+template <class Rule, bool WANT_F, bool WANT_K, bool ACCUM>
+__device__ __forceinline__ void gather_rows_mc(const GatherArgs& g, int32_t I0, int32_t I1, unsigned char* smem,
+                                               int32_t* pre, int32_t* rowo) {
+  constexpr int NEN = Rule::NEN, NPN = Rule::NPN, MC = 4, RPN = 3 * MC, TPI = 9 * MC;
+  constexpr int BLK = rows_mc_block<NEN>();
+  const int tid = threadIdx.x;
+  uint8_t* incn = smem;
+  double* lds = reinterpret_cast<double*>(smem + g.inc_cap);
+  const int nn = I1 - I0;
+  const int64_t row0 = (int64_t)RPN * I0, row1 = (int64_t)RPN * I1;
+  const int64_t seg0 = WANT_K ? g.row_off[row0] : 0, seg1 = WANT_K ? g.row_off[row1] : 0;
+  const int nseg = (int)(seg1 - seg0);
+  const int nrow = (int)(row1 - row0);
+  double* lf = lds + nseg;
+  for (int t = tid; t < nseg + nrow; t += blockDim.x) lds[t] = 0.0;
+  const int32_t inc0 = g.inc_off[I0];
+  for (int n = tid; n <= nn; n += blockDim.x) pre[n] = TPI * (g.inc_off[I0 + n] - inc0);
+  if constexpr (WANT_K)
+    for (int rr = tid; rr < nrow; rr += blockDim.x) rowo[rr] = (int32_t)(g.row_off[row0 + rr] - seg0);
+  __syncthreads();
+  for (int n = tid; n < nn; n += blockDim.x)
+    for (int j = pre[n] / TPI; j < pre[n + 1] / TPI; ++j) incn[j] = (uint8_t)n;
+  if constexpr (WANT_K) add_mass_term<MC>(g, I0, nn, lds, rowo);
+  __syncthreads();
+  const int ntask = pre[nn];
+  const float* blk = reinterpret_cast<const float*>(g.stage);
+  for (int t = tid; t < ntask; t += blockDim.x) {
+    const int jl = t / TPI, sl = t - TPI * jl, r = sl / 3, k = sl - 3 * r;
+    const int64_t j = inc0 + jl;
+    const int rl = RPN * incn[jl] + r;
+    const float* bj = blk + j * BLK;
+    if constexpr (WANT_K) {
+      float val[NEN];
+      const f32x4* p = reinterpret_cast<const f32x4*>(bj + (3 * r + k) * NEN);
+#pragma unroll
+      for (int u = 0; u < NEN / 4; ++u) {
+        const f32x4 w = p[u];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) val[4 * u + x] = w[x];
+      }
+      const int32_t v = g.inc[j];
+      const int64_t ea = (int64_t)(v >> 4) * NPN + (v & 15);
+      const uint32_t rw = *reinterpret_cast<const uint32_t*>(g.rank + ea * rank_stride(NPN));
+      double* dstp = lds + rowo[rl] + k;
+#pragma unroll
+      for (int b = 0; b < NEN; ++b) {
+        const int rank_b = (int)((rw >> (8 * (b >> 2))) & 255u);
+        atomicAdd(dstp + 3 * (MC * rank_b + (b & 3)), (double)val[b]);
+      }
+    }
+    if constexpr (WANT_F) atomicAdd(lf + rl, (double)bj[36 * NEN + 3 * r + k]);
+  }
+  __syncthreads();
+  if constexpr (WANT_K) write_segment<ACCUM>(g, row0, nrow, nseg, seg0, lds, rowo);
+  if constexpr (WANT_F) {
+    double* out = g.f + row0;
+    for (int t = tid; t < nrow; t += blockDim.x) out[t] = ACCUM ? out[t] + lf[t] : lf[t];
+  }
+}
+
+template <class Rule, bool WANT_F, bool WANT_K, bool ACCUM>
+__global__ __launch_bounds__(512) void k_gather_rows_mc(GatherArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t pre[kMaxRangeNodes + 1];
+  __shared__ int32_t rowo[kMaxRangeNodes * 12];
+  const int r = remap_tile(blockIdx.x, gridDim.x);
+  gather_rows_mc<Rule, WANT_F, WANT_K, ACCUM>(g, g.ranges[r], g.ranges[r + 1], smem, pre, rowo);
+}
+
+// ---------------------------------------------------------------------------
 // internal force alone (every element type)
 // ---------------------------------------------------------------------------
 // Pass 1 keeps each element's points in one workgroup: a lane per point forms
@@ -1191,6 +1390,55 @@ int launch_rows_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStr
   return TLFEA_OK;
 }
 
+template <class Rule>
+int launch_rows_mc_points(const Mesh& m, const AsmArgs& a, hipStream_t s) {
+  constexpr int EB = rows_mc_elems<Rule>();
+  const int64_t blocks = (m.n_elem + EB - 1) / EB;
+  if (blocks > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_elem_rows_mc<Rule>, dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s, a, m.d_incpos,
+                       (float*)m.d_stage);
+  TLFEA_HIP_CHECK(hipGetLastError());
+  return TLFEA_OK;
+}
+
+template <class Rule>
+int launch_rows_mc_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const GatherOptions& mt) {
+  const bool want_f = f != nullptr, want_k = vals != nullptr;
+  GatherArgs g{};
+  g.ranges = m.d_ranges;
+  g.inc_off = m.d_inc_off;
+  g.inc = m.d_inc;
+  g.row_off = m.d_row_off;
+  g.rank = m.d_rank;
+  g.stage = m.d_stage;
+  g.f = f;
+  g.vals = vals;
+  g.mass = mt.mass;
+  g.adj_off = m.d_adj_off;
+  g.inv_h = mt.inv_h;
+  g.row_off_u = mt.row_off_u;
+  g.inc_cap = (int)((m.max_range_inc + 15) / 16 * 16);
+  const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows) + g.inc_cap +
+                     (mt.row_off_u ? upper_table_bytes(m) : 0);
+  const dim3 grid((unsigned)m.n_ranges), blk(64 * m.tune.waves);
+#define TLFEA_GATHER(F, K, A)                                                   \
+  do {                                                                          \
+    if (int rc = allow_lds(k_gather_rows_mc<Rule, F, K, A>, lds)) return rc;    \
+    hipLaunchKernelGGL((k_gather_rows_mc<Rule, F, K, A>), grid, blk, lds, s, g); \
+  } while (0)
+  if (want_k && want_f) {
+    if (accum) TLFEA_GATHER(true, true, true); else TLFEA_GATHER(true, true, false);
+  } else if (want_k) {
+    if (accum) TLFEA_GATHER(false, true, true); else TLFEA_GATHER(false, true, false);
+  } else {
+    if (accum) TLFEA_GATHER(true, false, true); else TLFEA_GATHER(true, false, false);
+  }
+#undef TLFEA_GATHER
+  TLFEA_HIP_CHECK(hipGetLastError());
+  return TLFEA_OK;
+}
+
 template <typename R>
 int launch_points_prec(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s) {
   if (m.elem_type == TLFEA_T10) return launch_points_rule<RuleT10, R>(m, a, want_k, s);
@@ -1231,7 +1479,7 @@ bool use_rows(const Mesh& m, bool want_k) {
     const char* v = std::getenv("TLFEA_ELEMENT_ROWS");
     return !(v && v[0] == '0');
   }();
-  return on && want_k && m.elem_type == TLFEA_T10 && m.precision == TLFEA_MIXED && m.d_incpos && m.d_rank_inc;
+  return on && want_k && m.precision == TLFEA_MIXED && m.d_incpos && (m.elem_type != TLFEA_T10 || m.d_rank_inc);
 }
 
 bool use_force_blocks(const Mesh& m, bool want_k) {
@@ -1243,7 +1491,8 @@ bool use_force_blocks(const Mesh& m, bool want_k) {
 }
 
 size_t stage_bytes(const Mesh& m, bool want_k) {
-  if (use_rows(m, want_k)) return (size_t)m.n_elem * m.n_pn * kRowBlk * sizeof(float);
+  if (use_rows(m, want_k))
+    return (size_t)m.n_elem * m.n_pn * (m.elem_type == TLFEA_T10 ? kRowBlk : 36 * m.n_en + 36) * sizeof(float);
   const size_t r = m.precision == TLFEA_MIXED ? sizeof(float) : sizeof(double);
   if (use_force_blocks(m, want_k)) return (size_t)m.n_elem * m.n_pn * 3 * m.mc * r;
   return (size_t)m.n_elem * m.n_qp * (want_k ? kRecK : kRecF) * r;
@@ -1268,6 +1517,11 @@ int launch_zero(double* p, int64_t n, hipStream_t s) {
 int launch_points(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s) {
   if (use_force_blocks(m, want_k))
     return m.precision == TLFEA_MIXED ? launch_force_prec<float>(m, a, s) : launch_force_prec<double>(m, a, s);
+  if (use_rows(m, want_k) && m.elem_type != TLFEA_T10) {
+    if (m.elem_type == TLFEA_ANCF3243) return launch_rows_mc_points<RuleBeam>(m, a, s);
+    if (m.gl[0] == 3) return launch_rows_mc_points<RuleAncf<3, 3, 2>>(m, a, s);
+    return launch_rows_mc_points<RuleAncf<4, 4, 3>>(m, a, s);
+  }
   if (use_rows(m, want_k)) {
     const int64_t blocks = (m.n_elem + kRowElems - 1) / kRowElems;
     if (blocks > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
@@ -1288,6 +1542,10 @@ int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t
     int rc = f ? launch_zero(f, m.n_dof, s) : TLFEA_OK;
     return (rc || !vals) ? rc : launch_zero(vals, mt.row_off_u ? m.nnz_u : m.nnz, s);
   }
+  if (m.staged == 3 && m.elem_type == TLFEA_ANCF3243) return launch_rows_mc_nodes<RuleBeam>(m, f, vals, accum, s, mt);
+  if (m.staged == 3 && m.elem_type == TLFEA_ANCF3443)
+    return m.gl[0] == 3 ? launch_rows_mc_nodes<RuleAncf<3, 3, 2>>(m, f, vals, accum, s, mt)
+                        : launch_rows_mc_nodes<RuleAncf<4, 4, 3>>(m, f, vals, accum, s, mt);
   if (m.staged == 3) return launch_rows_nodes(m, f, vals, accum, s, mt);
   if (m.staged == 4) return vals ? TLFEA_ERR_INVALID : launch_force_sum(m, f, accum, s);
   if (m.precision == TLFEA_MIXED) return launch_nodes_prec<float>(m, f, vals, accum, s, mt);

@@ -115,7 +115,8 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
   b->gl0 = m0.gl[0];
   b->precision = m0.precision;
   b->rows = 1;
-  for (int i = 0; i < n_bodies; ++i) b->rows &= tlfea::use_rows(meshes[i]->m, true) ? 1 : 0;
+  for (int i = 0; i < n_bodies; ++i)
+    b->rows &= (meshes[i]->m.elem_type == TLFEA_T10 && tlfea::use_rows(meshes[i]->m, true)) ? 1 : 0;
   std::vector<BatchBody> bodies(n_bodies);
   b->dof_off.assign(n_bodies + 1, 0);
   b->nnz_off.assign(n_bodies + 1, 0);

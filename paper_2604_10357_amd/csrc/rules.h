@@ -62,6 +62,24 @@ struct RuleT10 {
   __device__ static double w_rt(int q) { return c_t10.w[q]; }
 };
 
+// Float copies of the ANCF gradient tables (element-row kernels, float32
+// arithmetic), read with a wave-uniform point index through the scalar cache.
+template <int NQ, int NEN>
+struct FloatGrad {
+  float v[NQ][NEN][3];
+};
+template <int NQ, int NEN, class T>
+constexpr FloatGrad<NQ, NEN> make_float_grad(const T& t) {
+  FloatGrad<NQ, NEN> f{};
+  for (int q = 0; q < NQ; ++q)
+    for (int a = 0; a < NEN; ++a)
+      for (int m = 0; m < 3; ++m) f.v[q][a][m] = (float)t.dS[q][a][m];
+  return f;
+}
+static __constant__ FloatGrad<18, 16> c_a332_f = make_float_grad<18, 16>(kAncf332);
+static __constant__ FloatGrad<48, 16> c_a443_f = make_float_grad<48, 16>(kAncf443);
+static __constant__ FloatGrad<12, 8> c_b322_f = make_float_grad<12, 8>(kBeam322);
+
 template <int NX, int NY, int NZ>
 struct RuleAncf {
   static constexpr int NEN = 16, NPN = 4, MC = 4, NQ = NX * NY * NZ;
@@ -74,6 +92,9 @@ struct RuleAncf {
   }
   __device__ static double dN_rt(int q, int a, int m) { return ctab().dS[q][a][m]; }
   __device__ static double w_rt(int q) { return ctab().w[q]; }
+  __device__ static float dNf_rt(int q, int a, int m) {
+    if constexpr (NX == 3) return c_a332_f.v[q][a][m]; else return c_a443_f.v[q][a][m];
+  }
 };
 
 // ANCF3243 beam, Gauss-Legendre 3 x 2 x 2 (two physical nodes of four coefficients)
@@ -82,6 +103,7 @@ struct RuleBeam {
   static constexpr double dN(int q, int a, int m) { return kBeam322.dS[q][a][m]; }
   __device__ static double dN_rt(int q, int a, int m) { return c_b322.dS[q][a][m]; }
   __device__ static double w_rt(int q) { return c_b322.w[q]; }
+  __device__ static float dNf_rt(int q, int a, int m) { return c_b322_f.v[q][a][m]; }
 };
 
 }  // namespace

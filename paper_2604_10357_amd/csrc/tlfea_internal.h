@@ -280,9 +280,10 @@ struct BatchArgs {
 MatParams make_params(int material, const double* params, double eta, double lam_v);
 
 // bytes of pass-1 records for a mesh / per record
-// Element-row path: T10 with the tangent in mixed precision (environment
-// TLFEA_ELEMENT_ROWS=0 switches it off).  Pass 1 then leaves one row block per
-// incidence instead of per-point records.
+// Element-row path: the tangent in mixed precision, every element type (the
+// environment variable TLFEA_ELEMENT_ROWS=0 switches it off; batches take it
+// for T10 only).  Pass 1 then leaves one row block per incidence instead of
+// per-point records.
 bool use_rows(const Mesh& m, bool want_k);
 // Force-only path (every element type; TLFEA_FORCE_BLOCKS=0 switches it off):
 // pass 1 leaves one float-or-double force block of 3 mc values per incidence.

@@ -164,9 +164,14 @@ int tlfea_get_slot_map(tlfea_mesh_t mesh, int64_t elem_begin, int64_t elem_count
 
 /* f_int(q, qdot) -> d_f (n_dof float64).  d_qdot may be NULL (zero velocity).
  * Needs the pattern (tlfea_build_csr_pattern): the per-node reduction uses
- * its node-to-element incidence.  The first call of each kind allocates the
- * mesh's per-point work buffer (n_elem x n_qp records of 96 values, float32 in
- * mixed precision) and synchronises; later calls do not allocate. */
+ * its node-to-element incidence.  Each element's force is summed over its
+ * points in one workgroup and left as one block of 3 mc values per (element,
+ * node) incidence (float32 in mixed precision) in the mesh's work buffer; the
+ * per-node sums then run in a fixed order, so repeated calls give the same
+ * bits.  The first call that needs a larger work buffer allocates it and
+ * synchronises; later calls do not allocate.
+ * For the CSR-valued calls below, d_vals may be NULL exactly when the pattern
+ * has no entries (a mesh without elements). */
 int tlfea_internal_force(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double* d_f,
                          void* stream);
 

@@ -534,27 +534,38 @@ TLFEA_API int tlfea_internal_force(tlfea_mesh_t mesh, const double* d_q, const d
   return run_assembly(mesh, d_q, d_qdot, 1.0, 0.0, d_f, nullptr, stream);
 }
 
+// A null values pointer stands for the empty output of a pattern without
+// entries (a mesh without elements); otherwise the values are required.
+static bool vals_given(tlfea_mesh_t mesh, const double* d_vals) {
+  return d_vals || (mesh && mesh->m.has_pattern && mesh->m.nnz == 0);
+}
+
+static int run_tangent(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double alpha, double beta,
+                       double* d_vals, void* stream) {
+  if (!vals_given(mesh, d_vals)) return TLFEA_ERR_INVALID;
+  if (!d_vals) return tlfea::check_call(mesh, d_q, true);  // nothing to compute
+  return run_assembly(mesh, d_q, d_qdot, alpha, beta, nullptr, d_vals, stream);
+}
+
 TLFEA_API int tlfea_tangent(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double h, double* d_vals,
                             void* stream) {
-  if (!d_vals) return TLFEA_ERR_INVALID;
-  return run_assembly(mesh, d_q, d_qdot, h, 1.0, nullptr, d_vals, stream);
+  return run_tangent(mesh, d_q, d_qdot, h, 1.0, d_vals, stream);
 }
 
 TLFEA_API int tlfea_tangent_ex(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double alpha,
                                double beta, double* d_vals, void* stream) {
-  if (!d_vals) return TLFEA_ERR_INVALID;
-  return run_assembly(mesh, d_q, d_qdot, alpha, beta, nullptr, d_vals, stream);
+  return run_tangent(mesh, d_q, d_qdot, alpha, beta, d_vals, stream);
 }
 
 TLFEA_API int tlfea_assemble(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double h, double* d_f,
                              double* d_vals, void* stream) {
-  if (!d_f || !d_vals) return TLFEA_ERR_INVALID;
+  if (!d_f || !vals_given(mesh, d_vals)) return TLFEA_ERR_INVALID;
   return run_assembly(mesh, d_q, d_qdot, h, 1.0, d_f, d_vals, stream);
 }
 
 TLFEA_API int tlfea_assemble_ex(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double alpha,
                                 double beta, double* d_f, double* d_vals, void* stream) {
-  if (!d_f || !d_vals) return TLFEA_ERR_INVALID;
+  if (!d_f || !vals_given(mesh, d_vals)) return TLFEA_ERR_INVALID;
   return run_assembly(mesh, d_q, d_qdot, alpha, beta, d_f, d_vals, stream);
 }
 

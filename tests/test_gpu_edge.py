@@ -1,0 +1,84 @@
+"""Edge cases of the HIP path against the oracle, through the C ABI: nodes that
+no element uses (empty CSR rows, zero forces, no mass) and meshes without
+elements, for every element type and both precisions."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2604_10357_amd import workloads as W
+from tests.gpu_util import TOL, cuda, make_mesh, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def bases():
+    return [("t10", W.t10_beam(2, 1, 1, 61, "t10", lx=0.2, ly=0.1, lz=0.1)),
+            ("shell", W.shell_plate(2, 62, "shell", thickness=0.02)),
+            ("beam", W.beam_3243(3, 63, "beam"))]
+
+
+def with_isolated(wl, extra=2):
+    """The same body plus `extra` pattern nodes that no element references."""
+    m = wl.mesh
+    mc = 1 if m.elem_type == W.T10 else 4
+    rng = np.random.default_rng(64)
+    Xe = rng.normal(5.0, 0.1, (extra * mc, 3))
+    q = np.concatenate([wl.q, Xe.ravel() + 0.01])
+    qd = np.concatenate([wl.qdot, rng.normal(0, 0.05, Xe.size)])
+    mesh = W.Mesh(m.elem_type, np.vstack([m.X, Xe]), m.conn, m.gl, m.thickness, getattr(m, "width", 0.0))
+    return W.Workload(wl.name + "_iso", mesh, wl.material, q, qd, None)
+
+
+CASES = bases()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,base", CASES, ids=[c[0] for c in CASES])
+def test_isolated_nodes(name, base, precision):
+    print(f"[gpu] isolated nodes {name} {precision}", flush=True)
+    wl = with_isolated(base)
+    m = make_mesh(wl, precision)
+    om = oracle.Mesh.of(wl.mesh)
+    omat = oracle.material_of(wl.material)
+    ro_ref, cols_ref = oracle.csr_pattern(om)
+    ro, cols = m.csr_pattern(on_device=False)
+    assert np.array_equal(ro.numpy(), ro_ref) and np.array_equal(cols.numpy(), cols_ref)
+    n0 = base.mesh.n_dof
+    assert np.all(np.diff(ro_ref)[n0:] == 0)
+    q, qd = cuda(wl.q), cuda(wl.qdot)
+    f, vals = m.assemble(q, qd, 1e-3, 1.0)
+    f_ref, v_ref = oracle.assemble(om, omat, wl.q, wl.qdot, 1e-3, 1.0, pattern=(ro_ref, cols_ref))
+    fh = f.cpu().numpy()
+    assert np.all(fh[n0:] == 0.0)
+    assert rel_err(fh, f_ref)[0] <= TOL[precision]
+    assert rel_err(vals.cpu().numpy(), v_ref)[0] <= TOL[precision]
+    fo = m.internal_force(q, qd).cpu().numpy()
+    assert np.all(fo[n0:] == 0.0) and rel_err(fo, f_ref)[0] <= TOL[precision]
+    # mass and gradient: isolated nodes have no mass rows, so g = f_int - f_ext there
+    m.build_mass(1000.0)
+    mv = m.mass_values().cpu().numpy()
+    assert rel_err(mv, oracle.mass_csr(om, 1000.0, (ro_ref, cols_ref)))[0] <= 1e-13
+    g = m.newton_gradient(qd, torch.zeros_like(qd), f, None, 1e-3).cpu().numpy()
+    assert np.array_equal(g[n0:], fh[n0:])
+    m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,base", CASES, ids=[c[0] for c in CASES])
+def test_mesh_without_elements(name, base, precision):
+    print(f"[gpu] no elements {name} {precision}", flush=True)
+    b = base.mesh
+    mesh = W.Mesh(b.elem_type, b.X, b.conn[:0].copy(), b.gl, b.thickness, getattr(b, "width", 0.0))
+    wl = W.Workload("empty", mesh, base.material, base.q, base.qdot, None)
+    m = make_mesh(wl, precision)
+    assert m.nnz == 0
+    ro, _ = m.csr_pattern(on_device=False)
+    assert np.all(ro.numpy() == 0)
+    q, qd = cuda(wl.q), cuda(wl.qdot)
+    f = torch.full((m.n_dof,), 7.0, dtype=torch.float64, device="cuda")
+    m.assemble(q, qd, 1e-3, 1.0, f=f)
+    assert torch.count_nonzero(f).item() == 0
+    fo = m.internal_force(q, qd)
+    assert torch.count_nonzero(fo).item() == 0
+    m.close()

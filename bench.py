@@ -30,6 +30,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (dense)
+FP64_PEAK_TFLOPS = 78.6
+
+
+def contraction_flop(wl):
+    """FLOPs per element of the tangent contraction alone (the arithmetic floor of
+    K_e): per point t_a = A g_a for every (a, i, k) (9 FMA each, 81 n_en) and every
+    3x3 block (a, b) from t_a (27 FMA each, 27 n_en^2); constitutive work and f
+    not counted."""
+    n_en = {1: 10, 2: 16, 3: 8}[wl.mesh.elem_type]
+    n_qp = 5 if wl.mesh.elem_type == 1 else int(np.prod(wl.mesh.gl))
+    return 2 * n_qp * (81 * n_en + 27 * n_en * n_en)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_t10_beam_200x20x20_mixed.json")
 
 
@@ -270,6 +282,12 @@ def bench_mesh(args, torch, wl, wname):
                                 f"{'' if kname == 'T10' else '_mc'} ({kname}, f + K)" if rows_path else
                                 f"k_stage_tile + k_gather ({kname}, f + K)"), "kernel_ms": ms,
                      "pass1_stage_ms": ms1, "pass2_gather_ms": ms2, "algorithmic_bytes": B},
+        # the same call against the vector arithmetic roofline (contraction FLOPs only)
+        "valu": {"flop_per_element": contraction_flop(wl),
+                 "achieved_TFLOPs": contraction_flop(wl) * n_el / (ms * 1e-3) / 1e12,
+                 "peak_TFLOPs": FP32_PEAK_TFLOPS if args.precision == "mixed" else FP64_PEAK_TFLOPS,
+                 "frac": contraction_flop(wl) * n_el / (ms * 1e-3) / 1e12
+                 / (FP32_PEAK_TFLOPS if args.precision == "mixed" else FP64_PEAK_TFLOPS)},
     }
     # Newton step pieces on the same mesh: H = M/h + h K_t (one call, the
     # mass term inside pass 2) and the gradient M (v - v_prev)/h + f_int;
@@ -341,6 +359,7 @@ def bench_mesh(args, torch, wl, wname):
         mesh.set_gather_shape(*[tuning["gather_shape"][k] for k in ("waves", "range_tasks", "range_values")])
         out["fp64"] = {"value": n_el / (ms64 * 1e-3), "ms_per_step": ms64, "tuning": tuning64, "pass1_stage_ms": ms64_1,
                        "pass2_gather_ms": ms64_2, "achieved_GBs": B / (ms64 * 1e-3) / 1e9,
+                       "valu_frac_fp64": contraction_flop(wl) * n_el / (ms64 * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                        "speedup_mixed_over_fp64": ms64 / ms}
         # mixed against the FP64 GPU result over the whole output
         out["mixed_vs_fp64_gpu"] = {

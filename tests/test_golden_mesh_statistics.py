@@ -1,6 +1,7 @@
 """The paper's printed mesh statistics fix the DOF conventions: three DOFs per
-T10 node and 4 coefficient vectors x 3 = 12 DOFs per ANCF3443 node on a
-structured n x n plate with (n+1)^2 nodes (Sec. 5.1 and Sec. 5.3 tables)."""
+T10 node, 4 coefficient vectors x 3 = 12 DOFs per ANCF3443 node on a
+structured n x n plate with (n+1)^2 nodes, and 12 DOFs per node of an
+n-element ANCF3243 chain with n + 1 nodes (Sec. 5.1, 5.2 and 5.3 tables)."""
 import math
 import os
 
@@ -39,3 +40,21 @@ def test_ancf3443_plate_counts_match_paper():
         assert mesh.n_coef == 4 * nodes
         assert mesh.n_dof == dofs
         assert len(np.unique(mesh.conn)) == nodes
+
+
+def test_ancf3243_chain_counts_match_paper():
+    import oracle
+    beam = [r for r in rows() if r[0] == "ANCF3243"]
+    assert len(beam) == 6
+    for _, res, dofs, nodes, elems in beam:
+        mesh = W.ancf3243_chain(elems)
+        assert mesh.n_elem == elems
+        assert mesh.n_coef == 4 * nodes
+        assert mesh.n_dof == dofs
+        assert len(np.unique(mesh.conn)) == nodes
+    # the oracle's pattern at RES0: an interior node couples to itself and its two
+    # neighbours (3 x 144 values per node), an end node to two
+    mesh = W.ancf3243_chain(beam[0][4])
+    ro, cols = oracle.csr_pattern(oracle.Mesh.of(mesh))
+    assert len(cols) == 144 * (3 * beam[0][4] + 1)
+

@@ -277,7 +277,9 @@ int tlfea_assemble_newton(tlfea_mesh_t mesh, const double* d_q, const double* d_
                           double* d_f, double* d_vals, void* stream);
 /* g = M (v - v_prev)/h + f_int - f_ext (Sec. 4.4.1, Eq. grad_L, without
  * constraint terms), n_dof float64 each, device; d_f_ext may be NULL (0).
- * A lane per node over its mass row; overwrites d_g.  h > 0.
+ * A group of lanes per node over its mass row; overwrites d_g.  h > 0.  On a
+ * T10 mesh the first call allocates a per-mesh buffer of n_dof doubles for
+ * v - v_prev (later calls do not allocate; calls on one mesh must not overlap).
  * TLFEA_ERR_INVALID before tlfea_build_mass. */
 int tlfea_newton_gradient(tlfea_mesh_t mesh, const double* d_v, const double* d_v_prev,
                           const double* d_f_int, const double* d_f_ext, double h, double* d_g,

@@ -150,6 +150,7 @@ void free_mesh(Mesh& m) {
   (void)hipFree(m.d_rank_inc);
   (void)hipFree(m.d_mass);
   (void)hipFree(m.d_solver);
+  (void)hipFree(m.d_dv);
   (void)hipFree(m.d_row_off_u);
   (void)hipFree(m.d_cols_u);
   (void)hipFree(m.d_stage);

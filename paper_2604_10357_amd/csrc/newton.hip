@@ -165,36 +165,62 @@ __global__ void k_mass_values(const int32_t* adj_off, const int32_t* row_off, co
     }
 }
 
-// g = M (v - v_prev) / h + f_int - f_ext: kGradLanes lanes per pattern node
-// split its mass row (consecutive entries: coalesced loads) and sum their parts
-// with a fixed butterfly of shuffles; the group's lanes then write the node's
-// 3 MC rows of g, lane j taking rows j, j + kGradLanes, ...
-constexpr int kGradLanes = 8;
+// g = M (v - v_prev) / h + f_int - f_ext: LANES lanes per pattern node split
+// its mass row (consecutive entries: coalesced loads), UNR entries per lane
+// and step in flight, and sum their parts with a fixed butterfly of shuffles;
+// the group's lanes then write the node's 3 MC rows of g, lane j taking rows
+// j, j + LANES, ...  T10 nodes have about 28 neighbours (8 lanes), ANCF nodes
+// 3 (beam) or 9 (shell) (4 lanes).
+#ifndef TLFEA_GRAD_UNROLL
+#define TLFEA_GRAD_UNROLL 2
+#endif
+template <int MC>
+constexpr int grad_lanes() { return MC == 1 ? 8 : 4; }
+__global__ void k_vdiff(const double* v, const double* vp, int64_t n, double* dv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dv[i] = v[i] - vp[i];
+}
+
+// T10 (about 28 neighbours per node) gathers v - v_prev formed once per DOF
+// (dv, vp null); ANCF (3 or 9) forms the difference at each gather.
 template <int MC>
 __global__ __launch_bounds__(256) void k_gradient(const int32_t* adj_off, const int32_t* adj, const double* mass,
-                                                  int64_t n_nodes, const double* v, const double* vp,
+                                                  int64_t n_nodes, const double* dv, const double* vp,
                                                   const double* fint, const double* fext, double inv_h, double* g) {
   constexpr int NR = 3 * MC;  // rows per node: (coefficient k, component d) at 3 k + d
+  constexpr int LANES = grad_lanes<MC>(), UNR = TLFEA_GRAD_UNROLL;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t I = t / kGradLanes;
-  const int sub = (int)(t % kGradLanes);
+  const int64_t I = t / LANES;
+  const int sub = (int)(t % LANES);
   double s[NR];
 #pragma unroll
   for (int j = 0; j < NR; ++j) s[j] = 0.0;
   if (I < n_nodes) {
-    for (int32_t x = adj_off[I] + sub; x < adj_off[I + 1]; x += kGradLanes) {
-      const int64_t J = adj[x];
-      const double* mx = mass + (int64_t)MC * MC * x;
+    const int32_t x1 = adj_off[I + 1];
+    for (int32_t x0 = adj_off[I] + sub; x0 < x1; x0 += LANES * UNR) {
+      int64_t J[UNR];
 #pragma unroll
-      for (int l = 0; l < MC; ++l) {
-        const int64_t c = 3 * (MC * J + l);
-        const double d0 = v[c] - vp[c], d1 = v[c + 1] - vp[c + 1], d2 = v[c + 2] - vp[c + 2];
+      for (int u = 0; u < UNR; ++u) J[u] = x0 + u * LANES < x1 ? adj[x0 + u * LANES] : -1;
 #pragma unroll
-        for (int k = 0; k < MC; ++k) {
-          const double m = mx[MC * k + l];
-          s[3 * k] += m * d0;
-          s[3 * k + 1] += m * d1;
-          s[3 * k + 2] += m * d2;
+      for (int u = 0; u < UNR; ++u) {
+        if (J[u] < 0) continue;
+        const double* mx = mass + (int64_t)MC * MC * (x0 + u * LANES);
+#pragma unroll
+        for (int l = 0; l < MC; ++l) {
+          const int64_t c = 3 * (MC * J[u] + l);
+          double d0 = dv[c], d1 = dv[c + 1], d2 = dv[c + 2];
+          if constexpr (MC != 1) {
+            d0 -= vp[c];
+            d1 -= vp[c + 1];
+            d2 -= vp[c + 2];
+          }
+#pragma unroll
+          for (int k = 0; k < MC; ++k) {
+            const double m = mx[MC * k + l];
+            s[3 * k] += m * d0;
+            s[3 * k + 1] += m * d1;
+            s[3 * k + 2] += m * d2;
+          }
         }
       }
     }
@@ -202,13 +228,13 @@ __global__ __launch_bounds__(256) void k_gradient(const int32_t* adj_off, const 
   // butterfly over the group: every lane ends with the full sums (all lanes
   // take part; groups never straddle a wave)
 #pragma unroll
-  for (int o = kGradLanes / 2; o > 0; o >>= 1)
+  for (int o = LANES / 2; o > 0; o >>= 1)
 #pragma unroll
-    for (int j = 0; j < NR; ++j) s[j] += __shfl_xor(s[j], o, kGradLanes);
+    for (int j = 0; j < NR; ++j) s[j] += __shfl_xor(s[j], o, LANES);
   if (I < n_nodes) {
 #pragma unroll
     for (int j = 0; j < NR; ++j)
-      if (j % kGradLanes == sub) {
+      if (j % LANES == sub) {
         const int64_t r = NR * I + j;
         g[r] = s[j] * inv_h + fint[r] - (fext ? fext[r] : 0.0);
       }
@@ -288,13 +314,27 @@ TLFEA_API int tlfea_newton_gradient(tlfea_mesh_t mesh, const double* d_v, const 
   if (rc) return rc;
   if (!d_v || !d_v_prev || !d_f_int || !d_g || !(h > 0.0) || !std::isfinite(h)) return TLFEA_ERR_INVALID;
   Mesh& m = mesh->m;
-  const dim3 grid(tlfea::blocks_of(m.n_pnodes * tlfea::kGradLanes, 256));
-  if (m.n_pnodes > 0 && m.mc == 1)
-    hipLaunchKernelGGL(tlfea::k_gradient<1>, grid, dim3(256), 0, (hipStream_t)stream, m.d_adj_off, m.d_adj, m.d_mass,
-                       m.n_pnodes, d_v, d_v_prev, d_f_int, d_f_ext, 1.0 / h, d_g);
-  else if (m.n_pnodes > 0)
-    hipLaunchKernelGGL(tlfea::k_gradient<4>, grid, dim3(256), 0, (hipStream_t)stream, m.d_adj_off, m.d_adj, m.d_mass,
-                       m.n_pnodes, d_v, d_v_prev, d_f_int, d_f_ext, 1.0 / h, d_g);
+  if (m.n_pnodes == 0) return TLFEA_OK;
+  const auto s = (hipStream_t)stream;
+  if (m.mc == 1) {
+    // v - v_prev once per DOF, so that the neighbour gathers read one vector
+    if (!m.d_dv) {
+      if (hipMalloc(&m.d_dv, sizeof(double) * m.n_dof) != hipSuccess) {
+        (void)hipGetLastError();
+        m.d_dv = nullptr;
+        return TLFEA_ERR_NOMEM;
+      }
+    }
+    hipLaunchKernelGGL(tlfea::k_vdiff, dim3(tlfea::blocks_of(m.n_dof, 256)), dim3(256), 0, s, d_v, d_v_prev,
+                       m.n_dof, m.d_dv);
+    hipLaunchKernelGGL(tlfea::k_gradient<1>, dim3(tlfea::blocks_of(m.n_pnodes * tlfea::grad_lanes<1>(), 256)),
+                       dim3(256), 0, s, m.d_adj_off, m.d_adj, m.d_mass, m.n_pnodes, m.d_dv, nullptr, d_f_int,
+                       d_f_ext, 1.0 / h, d_g);
+  } else {
+    hipLaunchKernelGGL(tlfea::k_gradient<4>, dim3(tlfea::blocks_of(m.n_pnodes * tlfea::grad_lanes<4>(), 256)),
+                       dim3(256), 0, s, m.d_adj_off, m.d_adj, m.d_mass, m.n_pnodes, d_v, d_v_prev, d_f_int,
+                       d_f_ext, 1.0 / h, d_g);
+  }
   TLFEA_HIP_CHECK(hipGetLastError());
   return TLFEA_OK;
 }

@@ -189,6 +189,7 @@ struct Mesh {
   int64_t nnz_u = -1;
   double density = 0.0;           // of the mass above (0: not built)
   double* d_solver = nullptr;     // first-order solver: iteration counter, norm partials, norms
+  double* d_dv = nullptr;         // gradient: v - v_prev per DOF (allocated by the first call)
   hipStream_t last_stream = nullptr;
 };
 

@@ -137,10 +137,19 @@ __device__ __forceinline__ void gather_nodal(const AsmArgs& a, int64_t e_lo, int
   }
 }
 
+#ifndef TLFEA_KIN_UNROLL
+#define TLFEA_KIN_UNROLL 4
+#endif
+
 // Displacement and velocity gradients at point q of element e from its nodal
 // values in LDS (ne: 6 doubles per coefficient): Hd = sum_a u_a (x) g_a,
 // Fd = sum_a qdot_a (x) g_a, with g_a = J0^-T dN_a (Sec. 4.3, Eq. F_assembly).
-template <class Rule>
+// PART: coefficients in steps of TLFEA_KIN_UNROLL instead of all at once (a
+// full unroll keeps every table load in flight; for the shell's 16
+// coefficients that caps the kernels at one wave per SIMD).  Measured per
+// kernel: steps for the shell everywhere and for the T10 force kernel, a full
+// unroll for the T10 element rows and the beam.
+template <class Rule, bool PART = (Rule::NEN > 10)>
 __device__ __forceinline__ void tile_kinematics(const AsmArgs& a, const double* ne, int64_t e, int q,
                                                 double (&Jinv)[9], double& det, double (&Hd)[9], double (&Fd)[9]) {
   constexpr int NEN = Rule::NEN;
@@ -150,8 +159,7 @@ __device__ __forceinline__ void tile_kinematics(const AsmArgs& a, const double* 
   double Du[9], Dv[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) Du[t] = Dv[t] = 0.0;
-#pragma unroll
-  for (int al = 0; al < NEN; ++al) {
+  auto add = [&](int al) __attribute__((always_inline)) {
     const double s = sc[al % 4];
     const double w0 = Rule::dN_rt(q, al, 0) * s, w1 = Rule::dN_rt(q, al, 1) * s, w2 = Rule::dN_rt(q, al, 2) * s;
 #pragma unroll
@@ -164,6 +172,13 @@ __device__ __forceinline__ void tile_kinematics(const AsmArgs& a, const double* 
       Dv[3 * i + 1] += v * w1;
       Dv[3 * i + 2] += v * w2;
     }
+  };
+  if constexpr (PART) {
+#pragma unroll TLFEA_KIN_UNROLL
+    for (int al = 0; al < NEN; ++al) add(al);
+  } else {
+#pragma unroll
+    for (int al = 0; al < NEN; ++al) add(al);
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -1178,7 +1193,7 @@ __global__ __launch_bounds__(kForceThreads) void k_elem_force(AsmArgs a, const i
   const int pl = act ? tid : 0;  // idle lanes evaluate point 0 and store nothing
   const int el = pl / NQ, q = pl - el * NQ;
   double Jinv[9], det, Hd[9], Fd[9];
-  tile_kinematics<Rule>(a, nod + 6 * NEN * el, e0 + el, q, Jinv, det, Hd, Fd);
+  tile_kinematics<Rule, (NEN > 8)>(a, nod + 6 * NEN * el, e0 + el, q, Jinv, det, Hd, Fd);
   __syncthreads();  // the nodal values are consumed: the LDS holds Phat from here on
   PointOut<R> o;
   const unsigned fl = point_update<R, false>(a.mp, Hd, Fd, det * Rule::w_rt(q), a.alpha, a.beta, o);

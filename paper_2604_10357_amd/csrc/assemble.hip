@@ -320,10 +320,10 @@ __device__ __forceinline__ void load_slot(const R* p, Slot<R, WANT_K>& s) {
 // coefficient al): with the slot of the task's element at point Q and the
 // task's scaled parent gradient d = dN_al(Q) (times the coefficient scale),
 //   t_n = sum_m d_m Ahat_imkn,  acc[b] += sum_n t_n dN_b,n(Q),  facc += Phat_ik d_k.
-template <class Rule, typename R, bool WANT_F, bool WANT_K, int Q, int NB>
-__device__ __forceinline__ void contract_point(const Slot<R, WANT_K>& s, R d0, R d1, R d2, int k, R (&acc)[NB],
+template <class Rule, typename R, bool WANT_F, bool WANT_K, int Q, int NB, bool KREC = WANT_K>
+__device__ __forceinline__ void contract_point(const Slot<R, KREC>& s, R d0, R d1, R d2, int k, R (&acc)[NB],
                                                R& facc) {
-  if constexpr (WANT_F) facc += (WANT_K ? s.v[9] : s.v[0]) * (k == 0 ? d0 : k == 1 ? d1 : d2);
+  if constexpr (WANT_F) facc += (KREC ? s.v[9] : s.v[0]) * (k == 0 ? d0 : k == 1 ? d1 : d2);
   if constexpr (WANT_K) {
     R tn[3];
 #pragma unroll
@@ -377,12 +377,12 @@ constexpr size_t wave_buf_bytes() {
 
 // The same with a run-time point index q (long rules); q is uniform across the
 // wave, so the gradients dN_b(q) come through the scalar cache.
-template <class Rule, typename R, bool WANT_F, bool WANT_K, int NB>
-__device__ __forceinline__ void contract_point_rt(const Slot<R, WANT_K>& s, int q, int al, int k, R sc_al,
+template <class Rule, typename R, bool WANT_F, bool WANT_K, int NB, bool KREC = WANT_K>
+__device__ __forceinline__ void contract_point_rt(const Slot<R, KREC>& s, int q, int al, int k, R sc_al,
                                                   R (&acc)[NB], R& facc) {
   const R d0 = (R)Rule::dN_rt(q, al, 0) * sc_al, d1 = (R)Rule::dN_rt(q, al, 1) * sc_al,
           d2 = (R)Rule::dN_rt(q, al, 2) * sc_al;
-  if constexpr (WANT_F) facc += (WANT_K ? s.v[9] : s.v[0]) * (k == 0 ? d0 : k == 1 ? d1 : d2);
+  if constexpr (WANT_F) facc += (KREC ? s.v[9] : s.v[0]) * (k == 0 ? d0 : k == 1 ? d1 : d2);
   if constexpr (WANT_K) {
     R tn[3];
 #pragma unroll
@@ -455,13 +455,16 @@ __device__ __forceinline__ void add_mass_term(const GatherArgs& g, int32_t I0, i
   }
 }
 
-template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM>
+// KREC: the records carry the tangent layout (a pass 1 with the tangent); the
+// force alone can also be taken from them (WANT_K false).
+template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM, bool KREC = WANT_K>
 __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, int32_t I1, unsigned char* smem,
                                              int32_t* pre, int32_t* rowo) {
+  static_assert(KREC || !WANT_K, "the tangent needs tangent records");
   constexpr int NQ = Rule::NQ, NPN = Rule::NPN, MC = Rule::MC, NEN = Rule::NEN;
   constexpr int RPN = 3 * MC;  // CSR rows per node
   constexpr int TPI = 3 * RPN; // tasks per incidence: (coefficient kind, row, component)
-  constexpr int REC = WANT_K ? kRecK : kRecF;
+  constexpr int REC = KREC ? kRecK : kRecF;
   constexpr int NI = chunk_incidences(TPI);
   using V = typename Vec4<R>::type;
   constexpr int PER = (int)(sizeof(V) / sizeof(R));
@@ -474,14 +477,14 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   static_assert(NQ % PB == 0, "point blocks must tile the rule");
   constexpr int PD = UNROLL ? (sizeof(R) == 4 ? NQ : 3) : PB;  // points whose pieces are in flight
   constexpr int NB = WANT_K ? NEN : 1;
-  constexpr bool DIRECT = direct_slots<Rule, R, WANT_K>();
-  constexpr int NS = staged_points<Rule, R, WANT_K>();  // points through the LDS copy (DIRECT: the first NS)
+  constexpr bool DIRECT = direct_slots<Rule, R, KREC>();
+  constexpr int NS = staged_points<Rule, R, KREC>();  // points through the LDS copy (DIRECT: the first NS)
   constexpr int PDS = DIRECT ? (NS > 0 ? NS : 1) : PD;     // staged points in flight
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
   // LDS: incidence -> node table, wave record buffers, CSR segment + forces
   uint8_t* incn = smem;
   R* wbuf = reinterpret_cast<R*>(smem + g.inc_cap) + wave * NI * REC;
-  double* lds = reinterpret_cast<double*>(smem + g.inc_cap + nwave * wave_buf_bytes<Rule, R, WANT_K>());
+  double* lds = reinterpret_cast<double*>(smem + g.inc_cap + nwave * wave_buf_bytes<Rule, R, KREC>());
   const int nn = I1 - I0;
   const int64_t row0 = (int64_t)RPN * I0, row1 = (int64_t)RPN * I1;
   const int64_t seg0 = WANT_K ? g.row_off[row0] : 0, seg1 = WANT_K ? g.row_off[row1] : 0;
@@ -565,7 +568,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
     const int64_t e = packed >> 4;
     const int a = packed & 15;
     const int al = MC * a + ca;
-    const R* mine = wbuf + (t / TPI - j0) * REC + (WANT_K ? kSlot * (3 * i + k) : 4 * i + k);
+    const R* mine = wbuf + (t / TPI - j0) * REC + (KREC ? kSlot * (3 * i + k) : 4 * i + k);
     // slot-map row of (e, a): one aligned vector load
     constexpr int RST = rank_stride(NPN);
     uint32_t rkw[RST / 4];
@@ -620,7 +623,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
       }
       sfor<0, NQ>([&](auto qc) __attribute__((always_inline)) {
         constexpr int q = decltype(qc)::value;
-        Slot<R, WANT_K> sl;
+        Slot<R, KREC> sl;
         if constexpr (DIRECT && q >= NS) {
 #pragma unroll
           for (int x = 0; x < kSlot; ++x) {
@@ -637,9 +640,10 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
             for (int kk = 0; kk < KC; ++kk)
               buf[q % PDS][kk] = stagev[src[kk] + (q + PDS) * VPP];
           }
-          load_slot<R, WANT_K>(mine, sl);
+          load_slot<R, KREC>(mine, sl);
         }
-        contract_point<Rule, R, WANT_F, WANT_K, q, NB>(sl, dna[3 * q], dna[3 * q + 1], dna[3 * q + 2], k, acc, facc);
+        contract_point<Rule, R, WANT_F, WANT_K, q, NB, KREC>(sl, dna[3 * q], dna[3 * q + 1], dna[3 * q + 2], k, acc,
+                                                             facc);
       });
     } else {
 #pragma unroll 1
@@ -656,9 +660,9 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
             for (int kk = 0; kk < KC; ++kk)
               buf[x][kk] = stagev[src[kk] + (uint32_t)(q + PB) * VPP];
           }
-          Slot<R, WANT_K> sl;
-          load_slot<R, WANT_K>(mine, sl);
-          contract_point_rt<Rule, R, WANT_F, WANT_K, NB>(sl, q, al, k, sc_al, acc, facc);
+          Slot<R, KREC> sl;
+          load_slot<R, KREC>(mine, sl);
+          contract_point_rt<Rule, R, WANT_F, WANT_K, NB, KREC>(sl, q, al, k, sc_al, acc, facc);
         });
       }
     }
@@ -684,13 +688,13 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   }
 }
 
-template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM>
+template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM, bool KREC>
 __global__ __launch_bounds__(512) void k_gather(GatherArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t pre[kMaxRangeNodes + 1];
   __shared__ int32_t rowo[kMaxRangeNodes * 3 * Rule::MC];
   const int r = remap_tile(blockIdx.x, gridDim.x);
-  gather_range<Rule, R, WANT_F, WANT_K, ACCUM>(g, g.ranges[r], g.ranges[r + 1], smem, pre, rowo);
+  gather_range<Rule, R, WANT_F, WANT_K, ACCUM, KREC>(g, g.ranges[r], g.ranges[r + 1], smem, pre, rowo);
 }
 
 template <class Rule, typename R>
@@ -1328,8 +1332,10 @@ bool records_addressable(int64_t n_elem, bool want_k) {
 
 template <class Rule, typename R>
 int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals, bool accum, hipStream_t s,
-                      const GatherOptions& mt) {
+                      const GatherOptions& mt, bool tangent_records) {
   const bool want_f = f != nullptr, want_k = vals != nullptr;
+  if (want_k && !tangent_records) return TLFEA_ERR_INVALID;
+  const bool krec = tangent_records;
   if (!records_addressable<Rule, R>(m.n_elem, want_k)) return TLFEA_ERR_TOO_LARGE;
   GatherArgs g{};
   g.ranges = m.d_ranges;
@@ -1348,20 +1354,22 @@ int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals,
   g.row_off_u = mt.row_off_u;
   g.inc_cap = (int)((m.max_range_inc + 15) / 16 * 16);
   const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows) + g.inc_cap +
-                     (size_t)m.tune.waves * (want_k ? wave_buf_bytes<Rule, R, true>() : wave_buf_bytes<Rule, R, false>()) +
+                     (size_t)m.tune.waves * (krec ? wave_buf_bytes<Rule, R, true>() : wave_buf_bytes<Rule, R, false>()) +
                      (mt.row_off_u ? upper_table_bytes(m) : 0);
   const dim3 grid((unsigned)m.n_ranges), blk(64 * m.tune.waves);
-#define TLFEA_GATHER(F, K, A)                                                \
-  do {                                                                       \
-    if (int rc = allow_lds(k_gather<Rule, R, F, K, A>, lds)) return rc;      \
-    hipLaunchKernelGGL((k_gather<Rule, R, F, K, A>), grid, blk, lds, s, g); \
+#define TLFEA_GATHER(F, K, A, KR)                                                \
+  do {                                                                           \
+    if (int rc = allow_lds(k_gather<Rule, R, F, K, A, KR>, lds)) return rc;      \
+    hipLaunchKernelGGL((k_gather<Rule, R, F, K, A, KR>), grid, blk, lds, s, g); \
   } while (0)
   if (want_k && want_f) {
-    if (accum) TLFEA_GATHER(true, true, true); else TLFEA_GATHER(true, true, false);
+    if (accum) TLFEA_GATHER(true, true, true, true); else TLFEA_GATHER(true, true, false, true);
   } else if (want_k) {
-    if (accum) TLFEA_GATHER(false, true, true); else TLFEA_GATHER(false, true, false);
+    if (accum) TLFEA_GATHER(false, true, true, true); else TLFEA_GATHER(false, true, false, true);
+  } else if (krec) {  // the force alone from tangent records
+    if (accum) TLFEA_GATHER(true, false, true, true); else TLFEA_GATHER(true, false, false, true);
   } else {
-    if (accum) TLFEA_GATHER(true, false, true); else TLFEA_GATHER(true, false, false);
+    if (accum) TLFEA_GATHER(true, false, true, false); else TLFEA_GATHER(true, false, false, false);
   }
 #undef TLFEA_GATHER
   TLFEA_HIP_CHECK(hipGetLastError());
@@ -1464,10 +1472,12 @@ int launch_points_prec(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t
 
 template <typename R>
 int launch_nodes_prec(const Mesh& m, double* f, double* vals, bool accum, hipStream_t s, const GatherOptions& mt) {
-  if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, R>(m, m.d_stage, f, vals, accum, s, mt);
-  if (m.elem_type == TLFEA_ANCF3243) return launch_nodes_rule<RuleBeam, R>(m, m.d_stage, f, vals, accum, s, mt);
-  if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, R>(m, m.d_stage, f, vals, accum, s, mt);
-  return launch_nodes_rule<RuleAncf<4, 4, 3>, R>(m, m.d_stage, f, vals, accum, s, mt);
+  const bool kr = m.staged == 2;  // tangent records (else force records)
+  if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, R>(m, m.d_stage, f, vals, accum, s, mt, kr);
+  if (m.elem_type == TLFEA_ANCF3243)
+    return launch_nodes_rule<RuleBeam, R>(m, m.d_stage, f, vals, accum, s, mt, kr);
+  if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, R>(m, m.d_stage, f, vals, accum, s, mt, kr);
+  return launch_nodes_rule<RuleAncf<4, 4, 3>, R>(m, m.d_stage, f, vals, accum, s, mt, kr);
 }
 
 template <class Rule, typename R>
@@ -1570,11 +1580,13 @@ int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t
 int launch_force_gather_f64(const Mesh& m, const double* records, double* out, hipStream_t s) {
   if (m.n_ranges == 0) return launch_zero(out, m.n_dof, s);
   const GatherOptions none;
-  if (m.elem_type == TLFEA_T10) return launch_nodes_rule<RuleT10, double>(m, records, out, nullptr, false, s, none);
+  if (m.elem_type == TLFEA_T10)
+    return launch_nodes_rule<RuleT10, double>(m, records, out, nullptr, false, s, none, false);
   if (m.elem_type == TLFEA_ANCF3243)
-    return launch_nodes_rule<RuleBeam, double>(m, records, out, nullptr, false, s, none);
-  if (m.gl[0] == 3) return launch_nodes_rule<RuleAncf<3, 3, 2>, double>(m, records, out, nullptr, false, s, none);
-  return launch_nodes_rule<RuleAncf<4, 4, 3>, double>(m, records, out, nullptr, false, s, none);
+    return launch_nodes_rule<RuleBeam, double>(m, records, out, nullptr, false, s, none, false);
+  if (m.gl[0] == 3)
+    return launch_nodes_rule<RuleAncf<3, 3, 2>, double>(m, records, out, nullptr, false, s, none, false);
+  return launch_nodes_rule<RuleAncf<4, 4, 3>, double>(m, records, out, nullptr, false, s, none, false);
 }
 
 int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tu, const BatchArgs& b,

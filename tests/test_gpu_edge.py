@@ -1,6 +1,7 @@
 """Edge cases of the HIP path against the oracle, through the C ABI: nodes that
-no element uses (empty CSR rows, zero forces, no mass) and meshes without
-elements, for every element type and both precisions."""
+no element uses (empty CSR rows, zero forces, no mass), meshes without
+elements, and the split / accumulating forms of the second pass, for every
+element type and both precisions."""
 import numpy as np
 import pytest
 import torch
@@ -81,4 +82,45 @@ def test_mesh_without_elements(name, base, precision):
     assert torch.count_nonzero(f).item() == 0
     fo = m.internal_force(q, qd)
     assert torch.count_nonzero(fo).item() == 0
+    m.close()
+
+
+SPLIT_CASES = [("t10", W.t10_beam(3, 2, 2, 65, "t10", lx=0.3, ly=0.2, lz=0.2)),
+               ("shell", W.shell_plate(3, 66, "shell", thickness=0.02)),
+               ("beam", W.beam_3243(11, 67, "beam"))]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,wl", SPLIT_CASES, ids=[c[0] for c in SPLIT_CASES])
+def test_split_and_accumulate_every_path(name, wl, precision):
+    """Pass 2 alone with f only, with K only and accumulating onto existing
+    values, after one pass 1 with the tangent: the same results as the fused
+    call on every element type and precision (element rows in mixed
+    precision, point records in FP64)."""
+    print(f"[gpu] split / accumulate {name} {precision}", flush=True)
+    m = make_mesh(wl, precision)
+    q, qd = cuda(wl.q), cuda(wl.qdot)
+    f, vals = m.assemble(q, qd, 2e-3, 1.0)
+    m.assemble_points(q, qd, 2e-3, 1.0, want_tangent=True)
+    f1 = torch.empty_like(f)
+    m.assemble_nodes(f1, None)
+    v1 = torch.empty_like(vals)
+    m.assemble_nodes(None, v1)
+    assert rel_err(f1.cpu().numpy(), f.cpu().numpy())[0] <= 1e-14
+    assert rel_err(v1.cpu().numpy(), vals.cpu().numpy())[0] <= 1e-13
+    base_f = torch.linspace(-1, 1, m.n_dof, dtype=torch.float64, device="cuda")
+    base_v = torch.linspace(2, 3, m.nnz, dtype=torch.float64, device="cuda")
+    f2, v2 = base_f.clone(), base_v.clone()
+    m.assemble_nodes(f2, v2, accumulate=True)
+    assert rel_err((f2 - base_f).cpu().numpy(), f.cpu().numpy())[0] <= 1e-12
+    assert rel_err((v2 - base_v).cpu().numpy(), vals.cpu().numpy())[0] <= 1e-12
+    f3, v3 = base_f.clone(), base_v.clone()
+    m.assemble_accumulate(q, qd, 2e-3, 1.0, f3, v3)
+    assert rel_err((f3 - base_f).cpu().numpy(), f.cpu().numpy())[0] <= 1e-12
+    assert rel_err((v3 - base_v).cpu().numpy(), vals.cpu().numpy())[0] <= 1e-12
+    # and the fused result against the oracle
+    om = oracle.Mesh.of(wl.mesh)
+    f_ref, v_ref = oracle.assemble(om, oracle.material_of(wl.material), wl.q, wl.qdot, 2e-3, 1.0)
+    assert rel_err(f.cpu().numpy(), f_ref)[0] <= TOL[precision]
+    assert rel_err(vals.cpu().numpy(), v_ref)[0] <= TOL[precision]
     m.close()

@@ -124,3 +124,33 @@ def test_split_and_accumulate_every_path(name, wl, precision):
     assert rel_err(f.cpu().numpy(), f_ref)[0] <= TOL[precision]
     assert rel_err(vals.cpu().numpy(), v_ref)[0] <= TOL[precision]
     m.close()
+
+
+@pytest.mark.parametrize("gl", [(3, 3, 2), (4, 4, 3)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_shell_batch(precision, gl):
+    """Shells of different sizes in one batched launch (point records for
+    every precision), against the oracle body by body."""
+    from paper_2604_10357_amd.api import TLBatch
+    print(f"[gpu] shell batch {gl} {precision}", flush=True)
+    wls = [W.shell_plate(n, 70 + n, f"s{n}", thickness=0.02, gl=gl) for n in (2, 4, 1, 3)]
+    meshes = [make_mesh(wl, precision) for wl in wls]
+    b = TLBatch(meshes)
+    q = cuda(np.concatenate([wl.q for wl in wls]))
+    qd = cuda(np.concatenate([wl.qdot for wl in wls]))
+    hs = np.linspace(1e-3, 2e-3, len(wls))
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        f, vals = b.assemble(q, qd, cuda(hs))
+    stream.synchronize()
+    for k, wl in enumerate(wls):
+        d0, d1 = b.dof_off[k], b.dof_off[k + 1]
+        z0, z1 = b.nnz_off[k], b.nnz_off[k + 1]
+        om = oracle.Mesh.of(wl.mesh)
+        f_ref, v_ref = oracle.assemble(om, oracle.material_of(wl.material), wl.q, wl.qdot, hs[k], 1.0)
+        assert rel_err(f[d0:d1].cpu().numpy(), f_ref)[0] <= TOL[precision], k
+        assert rel_err(vals[z0:z1].cpu().numpy(), v_ref)[0] <= TOL[precision], k
+    b.close()
+    for m in meshes:
+        m.close()

@@ -154,3 +154,25 @@ def test_shell_batch(precision, gl):
     b.close()
     for m in meshes:
         m.close()
+
+
+def test_vjp_damped_shell_443():
+    """The backward product on the 4x4x3 shell with Kelvin-Voigt damping
+    (cotangents for q, qdot and the material constants) against the oracle."""
+    print("[gpu] vjp shell 443 kv", flush=True)
+    wl = W.shell_plate(3, 75, "s443", thickness=0.02, gl=(4, 4, 3))
+    wl.material = W.Material(W.SVK, (2e9, 0.3, 0.0), 5e3, 5e3)
+    rng = np.random.default_rng(76)
+    wl.qdot = rng.normal(0, 0.05, wl.q.shape)
+    wl.w = rng.normal(0, 1.0, wl.q.shape)
+    m = make_mesh(wl, "fp64")
+    om = oracle.Mesh.of(wl.mesh)
+    gq_ref, gqd_ref, gp_ref = oracle.vjp(om, oracle.material_of(wl.material), wl.q, wl.qdot, wl.w)
+    gq, gqd, gp = m.vjp(cuda(wl.q), cuda(wl.qdot), cuda(wl.w))
+    assert rel_err(gq.cpu().numpy(), gq_ref)[0] <= 1e-12
+    assert np.abs(gqd_ref).max() > 0 and rel_err(gqd.cpu().numpy(), gqd_ref)[0] <= 1e-12
+    gp = gp.cpu().numpy()
+    for i in range(5):
+        if gp_ref[i] != 0.0:
+            assert abs(gp[i] - gp_ref[i]) <= 1e-11 * abs(gp_ref[i]), (i, gp[i], gp_ref[i])
+    m.close()

@@ -25,6 +25,8 @@ CASES = [
                                           material=W.Material(W.SVK, (1e7, 0.3, 0.0), 0.0, 0.0)))),
     ("t10_3x2x2_mr", undamped(W.t10_beam(3, 2, 2, 92, "t10_mr", lx=0.3, ly=0.2, lz=0.2))),
     ("ancf_4x3_332", undamped(W.shell_plate(4, 93, "ancf", thickness=0.02))),
+    ("ancf_3x3_443", undamped(W.shell_plate(3, 95, "ancf443", thickness=0.02, gl=(4, 4, 3)))),
+    ("beam_9", undamped(W.beam_3243(9, 96, "beam"))),
 ]
 
 

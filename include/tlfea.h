@@ -212,23 +212,29 @@ int tlfea_assemble_upper(tlfea_mesh_t mesh, const double* d_q, const double* d_q
 /* The two passes of every assembly call, exposed so that a caller can put
  * other work between them (e.g. pass 1 of the next mesh) or time them:
  *   tlfea_assemble_points: per element and quadrature point, the constitutive
- *     update (Sec. 4.3, Stage 1) and the point's stress and
- *     alpha dP/dF + beta dP/dFdot in parent coordinates with the quadrature
- *     volume folded in, stored in the mesh's work buffer (want_tangent = 0:
- *     stress only).  Allocates the buffer on first use (synchronising).
+ *     update (Sec. 4.3, Stage 1), then, into the mesh's work buffer, one of:
+ *     with the tangent in mixed precision, each element's rows of K_e
+ *     (alpha dP/dF + beta dP/dFdot contracted over its points, Eq.
+ *     tangent_block) and its force, one block per (element, node) incidence;
+ *     with the tangent in float64, per point the stress and the tangent in
+ *     parent coordinates with the quadrature volume folded in; without the
+ *     tangent (want_tangent = 0), each element's force, one block per
+ *     incidence.  Allocates the buffer when it is too small (synchronising).
  *   tlfea_assemble_nodes: per node, the sums of Eqs. fint_local / fint_global
  *     and Eq. tangent_block over the incident elements, written to d_f and / or
  *     d_vals (either may be NULL; d_vals needs want_tangent = 1); accumulate
  *     != 0 adds instead of overwriting.  Reads what the last
- *     tlfea_assemble_points of the same mesh left; returns TLFEA_ERR_INVALID
- *     if that does not exist, lacks the tangent or used another precision.
+ *     tlfea_assemble_points of the same mesh left, any number of times;
+ *     returns TLFEA_ERR_INVALID if that does not exist, lacks the tangent or
+ *     used another precision.
  * tlfea_assemble_ex(...) is exactly tlfea_assemble_points(..., 1, s) followed
  * by tlfea_assemble_nodes(..., 0, s).
- * Reproducibility: repeated calls on the same inputs agree to rounding (a few
- * units in the last place of the largest value), not bit for bit, because each
- * node range adds its contributions in the order its waves deliver them; an
- * atomic scatter per entry (Sec. 4.3, Eq. atomic_scatter; Sec. 4.4.2) behaves
- * the same way. */
+ * Reproducibility: calls with the tangent agree to rounding on repetition (a
+ * few units in the last place of the largest value), not bit for bit, because
+ * each node range adds its contributions in the order its waves deliver them;
+ * an atomic scatter per entry (Sec. 4.3, Eq. atomic_scatter; Sec. 4.4.2)
+ * behaves the same way.  The force alone (want_tangent = 0, and
+ * tlfea_internal_force) is summed in a fixed order and repeats bit for bit. */
 int tlfea_assemble_points(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double alpha,
                           double beta, int32_t want_tangent, void* stream);
 int tlfea_assemble_nodes(tlfea_mesh_t mesh, double* d_f, double* d_vals, int32_t accumulate,

@@ -42,7 +42,13 @@ def contraction_flop(wl):
     n_en = {1: 10, 2: 16, 3: 8}[wl.mesh.elem_type]
     n_qp = 5 if wl.mesh.elem_type == 1 else int(np.prod(wl.mesh.gl))
     return 2 * n_qp * (81 * n_en + 27 * n_en * n_en)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_t10_beam_200x20x20_mixed.json")
+# committed counter reports: file and the two kernels of the mixed call, per workload
+TRAFFIC = {
+    "t10_beam": ("hbm_traffic_t10_beam_200x20x20_mixed.json",
+                 ("k_elem_rows<RuleT10>", "k_gather_rows<true, true, false>")),
+    "ancf_beam": ("hbm_traffic_ancf3243_chain_500000_mixed.json",
+                  ("k_elem_rows_mc<RuleBeam>", "k_gather_rows_mc<RuleBeam, true, true, false>")),
+}
 
 
 def algorithmic_bytes(n_el, n_dof, nnz, n_pn=10, geo_bytes=80, extra_per_elem=0, want_k=True):
@@ -66,25 +72,28 @@ def mesh_bytes(wl, nnz, affine=True):
     return algorithmic_bytes(m.n_elem, m.n_dof, nnz, m.conn.shape[1], 80 if affine else 80 * nq, 16)
 
 
-def measured_traffic(precision, shape):
-    """HBM bytes per call of the two kernels from the committed counter report
-    (FETCH_SIZE / WRITE_SIZE calibrated on a 1 GiB copy), or None when the
-    report is missing, is for another precision or pass-2 launch shape, or the
-    kernels changed since."""
-    if precision != "mixed" or not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(wname, precision, shape):
+    """HBM bytes per call of the two kernels from the workload's committed
+    counter report (FETCH_SIZE / WRITE_SIZE calibrated on a 1 GiB copy), or
+    None when there is none, or it is for another precision or pass-2 launch
+    shape, or the kernels changed since."""
+    if precision != "mixed" or wname not in TRAFFIC:
+        return None
+    fname, kernels = TRAFFIC[wname]
+    path = os.path.join(ROOT, "profiles", fname)
+    if not os.path.exists(path):
         return None
     from paper_2604_10357_amd import pmc
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         rep = json.load(fh)
     if rep.get("kernel_source_sha256") != pmc.kernel_source_hash():
         return None
     if rep.get("gather_shape", pmc.DEFAULT_SHAPE) != shape:
         return None
     ks = rep["kernels"]
-    names = [k for k in ks if k.startswith("k_elem_rows<RuleT10>") or k.startswith("k_gather_rows<true, true, false>")]
-    if len(names) != 2:
+    if any(k not in ks for k in kernels):
         return None
-    return sum(ks[k]["hbm_bytes"] for k in names)
+    return sum(ks[k]["hbm_bytes"] for k in kernels)
 
 
 def time_calls(fn, steps, torch):
@@ -253,7 +262,7 @@ def bench_mesh(args, torch, wl, wname):
     # algorithmic bytes are set against the time of the whole call
     B = mesh_bytes(wl, nnz)
     achieved = B / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.precision, tuning["gather_shape"]) if wname == "t10_beam" else None
+    traffic = measured_traffic(wname, args.precision, tuning["gather_shape"])
     kname = {1: "T10", 2: "ANCF3443", 3: "ANCF3243"}[wl.mesh.elem_type]
     # the tangent in mixed precision takes the element-row kernels
     rows_path = args.precision == "mixed" and os.environ.get("TLFEA_ELEMENT_ROWS") != "0"

@@ -2,16 +2,17 @@
 
 Run under ``rocprofv3 --pmc``, once per counter (FETCH_SIZE, then WRITE_SIZE):
 
-    rocprofv3 --pmc FETCH_SIZE -d <dir>/fetch -o pmc -- python3 -m paper_2604_10357_amd.pmc run [W T V]
-    rocprofv3 --pmc WRITE_SIZE -d <dir>/write -o pmc -- python3 -m paper_2604_10357_amd.pmc run [W T V]
-    python3 -m paper_2604_10357_amd.pmc report <dir> <out.json> [W T V]
+    rocprofv3 --pmc FETCH_SIZE -d <dir>/fetch -o pmc -- python3 -m paper_2604_10357_amd.pmc run [MESH] [W T V]
+    rocprofv3 --pmc WRITE_SIZE -d <dir>/write -o pmc -- python3 -m paper_2604_10357_amd.pmc run [MESH] [W T V]
+    python3 -m paper_2604_10357_amd.pmc report <dir> <out.json> [MESH] [W T V]
 
-W T V is the pass-2 launch shape (waves, range_tasks, range_values) the
-assemblies use; without it, the library's default.
+MESH is `t10` (default: the 480,000-element T10 beam, Mooney-Rivlin +
+Kelvin-Voigt) or `beam` (the 500,000-element ANCF3243 chain, SVK); W T V is the
+pass-2 launch shape (waves, range_tasks, range_values) the assemblies use;
+without it, the default shape of the T10 beam.
 
-The workload assembles the 480,000-element T10 beam (Mooney-Rivlin +
-Kelvin-Voigt, mixed precision) three times and copies a 1 GiB device buffer
-twice.  The copy has known traffic (1 GiB read, 1 GiB written) and calibrates
+The workload assembles the mesh (mixed precision) three times and copies a
+1 GiB device buffer twice.  The copy has known traffic (1 GiB read, 1 GiB written) and calibrates
 each counter: FETCH_SIZE and WRITE_SIZE are scaled by 1 GiB divided by what
 they report for the copy.  The report stores, per kernel, the average
 counter values per dispatch, the calibrated HBM bytes per launch, and the
@@ -45,6 +46,10 @@ def kernel_source_hash() -> str:
 DEFAULT_SHAPE = {"waves": 4, "range_tasks": 768, "range_values": 2048}  # T10 built in mixed precision
 
 
+MESHES = {"t10": ("config5", "t10_beam_200x20x20_mr_kv mixed"),
+          "beam": ("beam_res32", "ancf3243_chain_500000_svk mixed")}
+
+
 def _shape(args) -> dict:
     if not args:
         return dict(DEFAULT_SHAPE)
@@ -52,13 +57,20 @@ def _shape(args) -> dict:
     return {"waves": w, "range_tasks": t, "range_values": v}
 
 
-def run(shape: dict) -> None:
+def _mesh_and_shape(args):
+    mesh = "t10"
+    if args and args[0] in MESHES:
+        mesh, args = args[0], args[1:]
+    return mesh, _shape(args)
+
+
+def run(shape: dict, mesh: str = "t10") -> None:
     import torch
 
     from . import workloads as W
     from .api import TLMesh
 
-    wl = W.config5()
+    wl = getattr(W, MESHES[mesh][0])()
     m = TLMesh(wl.mesh, wl.material, "mixed")
     m.build_pattern()
     m.set_gather_shape(shape["waves"], shape["range_tasks"], shape["range_values"])
@@ -91,8 +103,8 @@ def _per_kernel(db_dir: str, counter: str) -> dict:
     return out
 
 
-def report(base: str, out_json: str, shape: dict) -> dict:
-    res = {"workload": "t10_beam_200x20x20_mr_kv mixed", "gather_shape": shape,
+def report(base: str, out_json: str, shape: dict, mesh: str = "t10") -> dict:
+    res = {"workload": MESHES[mesh][1], "gather_shape": shape,
            "kernel_source_sha256": kernel_source_hash(), "copy_bytes": COPY_BYTES, "kernels": {}}
     for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
         per = _per_kernel(os.path.join(base, sub), counter)
@@ -116,10 +128,12 @@ def report(base: str, out_json: str, shape: dict) -> dict:
 
 
 if __name__ == "__main__":
-    if len(sys.argv) in (2, 5) and sys.argv[1] == "run":
-        run(_shape(sys.argv[2:]))
-    elif len(sys.argv) in (4, 7) and sys.argv[1] == "report":
-        print(json.dumps(report(sys.argv[2], sys.argv[3], _shape(sys.argv[4:])), indent=1))
+    if len(sys.argv) in (2, 3, 5, 6) and sys.argv[1] == "run":
+        mesh, shape = _mesh_and_shape(sys.argv[2:])
+        run(shape, mesh)
+    elif len(sys.argv) in (4, 5, 7, 8) and sys.argv[1] == "report":
+        mesh, shape = _mesh_and_shape(sys.argv[4:])
+        print(json.dumps(report(sys.argv[2], sys.argv[3], shape, mesh), indent=1))
     else:
         print(__doc__)
         sys.exit(2)

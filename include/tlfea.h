@@ -281,6 +281,14 @@ int tlfea_get_mass(tlfea_mesh_t mesh, double* d_vals, void* stream);
  * write like K.  h > 0.  TLFEA_ERR_INVALID before tlfea_build_mass. */
 int tlfea_assemble_newton(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double h,
                           double* d_f, double* d_vals, void* stream);
+/* The same Newton matrix in the upper-triangle storage a Cholesky solver takes
+ * (Sec. 4.6): row r of d_vals_upper (nnz_upper float64) holds the entries of
+ * H's row r from its diagonal on, on the pattern of tlfea_build_upper_pattern.
+ * Only for materials without Kelvin-Voigt damping (H = M/h + h df/dq is then
+ * symmetric); TLFEA_ERR_UNSUPPORTED otherwise, TLFEA_ERR_INVALID before
+ * tlfea_build_mass or tlfea_build_upper_pattern.  d_f may be NULL. */
+int tlfea_assemble_newton_upper(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double h,
+                                double* d_f, double* d_vals_upper, void* stream);
 /* g = M (v - v_prev)/h + f_int - f_ext (Sec. 4.4.1, Eq. grad_L, without
  * constraint terms), n_dof float64 each, device; d_f_ext may be NULL (0).
  * A group of lanes per node over its mass row; overwrites d_g.  h > 0.  On a

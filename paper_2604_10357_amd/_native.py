@@ -30,7 +30,8 @@ EXPORTED = [
     "tlfea_batch_destroy", "tlfea_batch_offsets", "tlfea_batch_assemble", "tlfea_batch_assemble_loop",
     "tlfea_mesh_set_gather_shape", "tlfea_mesh_get_gather_shape", "tlfea_mesh_autotune",
     "tlfea_batch_set_gather_shape", "tlfea_batch_get_gather_shape", "tlfea_batch_autotune",
-    "tlfea_build_mass", "tlfea_get_mass", "tlfea_assemble_newton", "tlfea_newton_gradient",
+    "tlfea_build_mass", "tlfea_get_mass", "tlfea_assemble_newton", "tlfea_assemble_newton_upper",
+    "tlfea_newton_gradient",
     "tlfea_build_upper_pattern", "tlfea_get_csr_pattern_upper", "tlfea_assemble_upper", "tlfea_adamw_solve",
 ]
 
@@ -119,6 +120,7 @@ def lib() -> ctypes.CDLL:
         "tlfea_build_mass": ([vp, dbl], ctypes.c_int),
         "tlfea_get_mass": ([vp, vp, vp], ctypes.c_int),
         "tlfea_assemble_newton": ([vp, vp, vp, dbl, vp, vp, vp], ctypes.c_int),
+        "tlfea_assemble_newton_upper": ([vp, vp, vp, dbl, vp, vp, vp], ctypes.c_int),
         "tlfea_newton_gradient": ([vp, vp, vp, vp, vp, dbl, vp, vp], ctypes.c_int),
         "tlfea_build_upper_pattern": ([vp, P(i64)], ctypes.c_int),
         "tlfea_get_csr_pattern_upper": ([vp, vp, vp, i32, vp], ctypes.c_int),

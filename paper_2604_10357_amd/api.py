@@ -231,6 +231,16 @@ class TLMesh:
                 "tlfea_assemble_newton")
         return f, vals
 
+    def assemble_newton_upper(self, q, qdot, h: float, f=None, vals_upper=None):
+        """f_int and the upper triangle of H = M/h + h df/dq (undamped materials)."""
+        f = torch.empty(self.n_dof, dtype=torch.float64, device=q.device) if f is None else f
+        n = self.nnz_upper
+        vals_upper = torch.empty(n, dtype=torch.float64, device=q.device) if vals_upper is None else vals_upper
+        N.check(N.lib().tlfea_assemble_newton_upper(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof),
+                                                    float(h), _ptr(f, n=self.n_dof), _ptr(vals_upper, n=n),
+                                                    _stream()), "tlfea_assemble_newton_upper")
+        return f, vals_upper
+
     def newton_gradient(self, v, v_prev, f_int, f_ext, h: float, out=None):
         """g = M (v - v_prev)/h + f_int - f_ext (f_ext may be None)."""
         out = torch.empty(self.n_dof, dtype=torch.float64, device=v.device) if out is None else out

@@ -352,3 +352,20 @@ TLFEA_API int tlfea_assemble_newton(tlfea_mesh_t mesh, const double* d_q, const 
   mt.inv_h = 1.0 / h;
   return tlfea::launch_nodes(m, d_f, d_vals, false, (hipStream_t)stream, mt);
 }
+
+TLFEA_API int tlfea_assemble_newton_upper(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double h,
+                                          double* d_f, double* d_vals_upper, void* stream) {
+  int rc = mass_ready(mesh);
+  if (rc) return rc;
+  if (!d_q || !d_vals_upper || !(h > 0.0) || !std::isfinite(h)) return TLFEA_ERR_INVALID;
+  Mesh& m = mesh->m;
+  if (!m.d_row_off_u) return TLFEA_ERR_INVALID;
+  // M/h + h df/dq is symmetric for the hyperelastic laws; the Kelvin-Voigt part is not
+  if (m.kv_eta != 0.0 || m.kv_lambda != 0.0) return TLFEA_ERR_UNSUPPORTED;
+  if ((rc = tlfea_assemble_points(mesh, d_q, d_qdot, h, 1.0, 1, stream))) return rc;
+  tlfea::GatherOptions mt;
+  mt.mass = m.d_mass;
+  mt.inv_h = 1.0 / h;
+  mt.row_off_u = m.d_row_off_u;
+  return tlfea::launch_nodes(m, d_f, d_vals_upper, false, (hipStream_t)stream, mt);
+}

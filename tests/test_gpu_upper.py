@@ -92,3 +92,54 @@ def test_upper_error_paths():
         d.assemble_upper(cuda(damped.q), cuda(damped.qdot), 1e-3, 1.0)
     assert e.value.status == -2
     d.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,wl", CASES, ids=[c[0] for c in CASES])
+def test_newton_matrix_upper(name, wl, precision):
+    """H = M/h + h df/dq in upper-triangle storage: against the oracle's mass and
+    tangent cut at the diagonal, and against the full GPU Newton matrix."""
+    print(f"[gpu] newton upper {name} {precision}", flush=True)
+    rho, h = 1100.0, 2e-3
+    m = make_mesh(wl, precision)
+    m.build_mass(rho)
+    m.build_upper_pattern()
+    om = oracle.Mesh.of(wl.mesh)
+    ro, cols = oracle.csr_pattern(om)
+    rng = np.random.default_rng(97)
+    v = rng.normal(0, 0.02, wl.mesh.n_dof)
+    q = wl.q + h * v
+    f_u, H_u = m.assemble_newton_upper(cuda(q), cuda(v), h)
+    f_ref, K_ref = oracle.assemble(om, oracle.material_of(wl.material), q, v, h, 1.0, pattern=(ro, cols))
+    H_ref = oracle.mass_csr(om, rho, (ro, cols)) / h + K_ref
+    _, _, Hu_ref = upper_of(ro, cols, H_ref)
+    assert rel_err(f_u.cpu().numpy(), f_ref)[0] <= TOL[precision]
+    assert rel_err(H_u.cpu().numpy(), Hu_ref)[0] <= TOL[precision]
+    _, H_full = m.assemble_newton(cuda(q), cuda(v), h)
+    _, _, Hu_full = upper_of(ro, cols, H_full.cpu().numpy())
+    assert rel_err(H_u.cpu().numpy(), Hu_full)[0] <= 1e-13
+    m.close()
+
+
+def test_newton_matrix_upper_errors():
+    print("[gpu] newton upper errors", flush=True)
+    wl = CASES[0][1]
+    m = make_mesh(wl, "mixed")
+    q = cuda(wl.q)
+    m.nnz_upper = m.nnz
+    with pytest.raises(TlfeaError) as e:  # no mass
+        m.assemble_newton_upper(q, q, 1e-3)
+    assert e.value.status == -1
+    m.build_mass(1000.0)
+    with pytest.raises(TlfeaError) as e:  # no upper pattern
+        m.assemble_newton_upper(q, q, 1e-3)
+    assert e.value.status == -1
+    m.close()
+    damped = W.t10_beam(2, 2, 1, 98, "damped", lx=0.2, ly=0.2, lz=0.1)
+    d = make_mesh(damped, "mixed")
+    d.build_mass(1000.0)
+    d.build_upper_pattern()
+    with pytest.raises(TlfeaError) as e:
+        d.assemble_newton_upper(cuda(damped.q), cuda(damped.qdot), 1e-3)
+    assert e.value.status == -2
+    d.close()

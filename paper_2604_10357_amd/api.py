@@ -93,6 +93,7 @@ class TLMesh:
         self.precision = precision
 
     def info(self):
+        """Sizes of the mesh: n_dof, n_elem, nnz (-1 before the pattern), n_en, n_qp."""
         n_dof, n_el, nnz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         n_en, n_qp = ctypes.c_int32(), ctypes.c_int32()
         N.check(N.lib().tlfea_mesh_info(self._h, ctypes.byref(n_dof), ctypes.byref(n_el), ctypes.byref(nnz),
@@ -101,12 +102,14 @@ class TLMesh:
 
     # -- pattern
     def build_pattern(self) -> int:
+        """Build the CSR pattern, slot map and node ranges once (tlfea_build_csr_pattern); returns nnz."""
         nnz = ctypes.c_int64()
         N.check(N.lib().tlfea_build_csr_pattern(self._h, ctypes.byref(nnz)), "tlfea_build_csr_pattern")
         self.nnz = nnz.value
         return self.nnz
 
     def csr_pattern(self, on_device: bool = True):
+        """(row_offsets, col_indices) of the pattern, int32, on the device or the host."""
         dev = "cuda" if on_device else "cpu"
         ro = torch.empty(self.n_dof + 1, dtype=torch.int32, device=dev)
         cols = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)[: self.nnz]
@@ -116,6 +119,7 @@ class TLMesh:
         return ro, cols
 
     def slot_map(self, e0: int = 0, ne: Optional[int] = None, on_device: bool = True):
+        """CSR position of every entry of the element matrices of elements [e0, e0 + ne), (ne, 3 n_en, 3 n_en) int32."""
         ne = self.n_elem - e0 if ne is None else ne
         nd = 3 * self.n_en
         dev = "cuda" if on_device else "cpu"
@@ -126,12 +130,14 @@ class TLMesh:
 
     # -- compute
     def internal_force(self, q, qdot=None, out=None):
+        """f_int(q, qdot) (qdot may be None: zero velocity), float64, n_dof."""
         out = torch.empty(self.n_dof, dtype=torch.float64, device=q.device) if out is None else out
         N.check(N.lib().tlfea_internal_force(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof),
                                              _ptr(out, n=self.n_dof), _stream()), "tlfea_internal_force")
         return out
 
     def tangent(self, q, qdot=None, h: float = 1.0, out=None, alpha=None, beta=None):
+        """CSR values of alpha df/dq + beta df/dqdot, (alpha, beta) = (h, 1) unless given."""
         out = torch.empty(self.nnz, dtype=torch.float64, device=q.device) if out is None else out
         a = h if alpha is None else alpha
         b = 1.0 if beta is None else beta
@@ -140,6 +146,7 @@ class TLMesh:
         return out
 
     def assemble(self, q, qdot=None, alpha: float = 1.0, beta: float = 1.0, f=None, vals=None):
+        """f_int and the CSR values of alpha df/dq + beta df/dqdot in one call."""
         f = torch.empty(self.n_dof, dtype=torch.float64, device=q.device) if f is None else f
         vals = torch.empty(self.nnz, dtype=torch.float64, device=q.device) if vals is None else vals
         N.check(N.lib().tlfea_assemble_ex(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof), float(alpha),
@@ -148,22 +155,26 @@ class TLMesh:
         return f, vals
 
     def assemble_accumulate(self, q, qdot=None, alpha: float = 1.0, beta: float = 1.0, f=None, vals=None):
+        """As assemble, adding onto f and vals instead of overwriting them."""
         N.check(N.lib().tlfea_assemble_accumulate(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof),
                                                   float(alpha), float(beta), _ptr(f, n=self.n_dof),
                                                   _ptr(vals, n=self.nnz), _stream()), "tlfea_assemble_accumulate")
         return f, vals
 
     def assemble_points(self, q, qdot=None, alpha: float = 1.0, beta: float = 1.0, want_tangent: bool = True):
+        """Pass 1 alone: the per-element work of an assembly into the mesh's work buffer."""
         N.check(N.lib().tlfea_assemble_points(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof),
                                               float(alpha), float(beta), int(want_tangent), _stream()),
                 "tlfea_assemble_points")
 
     def assemble_nodes(self, f=None, vals=None, accumulate: bool = False):
+        """Pass 2 alone: f and / or the CSR values from what the last pass 1 left."""
         N.check(N.lib().tlfea_assemble_nodes(self._h, _ptr(f, n=self.n_dof), _ptr(vals, n=self.nnz),
                                              int(accumulate), _stream()), "tlfea_assemble_nodes")
         return f, vals
 
     def vjp(self, q, qdot, w, want_q=True, want_qdot=True, want_params=True):
+        """(df/dq)^T w, (df/dqdot)^T w and d(w.f)/d(p0, p1, p2, kv_eta, kv_lambda), float64."""
         dev = q.device
         gq = torch.empty(self.n_dof, dtype=torch.float64, device=dev) if want_q else None
         gqd = torch.empty(self.n_dof, dtype=torch.float64, device=dev) if want_qdot else None
@@ -174,6 +185,7 @@ class TLMesh:
         return gq, gqd, gp
 
     def build_upper_pattern(self) -> int:
+        """Build the upper-triangle pattern (rows cut at the diagonal); returns nnz_upper."""
         n = ctypes.c_int64()
         N.check(N.lib().tlfea_build_upper_pattern(self._h, ctypes.byref(n)), "tlfea_build_upper_pattern")
         self.nnz_upper = n.value
@@ -250,6 +262,7 @@ class TLMesh:
         return out
 
     def set_gather_shape(self, waves: int, range_tasks: int, range_values: int):
+        """Set the pass-2 launch shape (waves per workgroup, tasks and values per node range)."""
         sh = N.GatherShape(waves, range_tasks, range_values)
         N.check(N.lib().tlfea_mesh_set_gather_shape(self._h, ctypes.byref(sh)), "tlfea_mesh_set_gather_shape")
 
@@ -272,6 +285,7 @@ class TLMesh:
         return sh.as_dict(), ms.value, f, vals
 
     def runtime_flags(self) -> int:
+        """Flags raised since the last read (bit 0: det F <= 0, bit 1: non-finite stress); clears them."""
         fl = ctypes.c_uint32()
         N.check(N.lib().tlfea_get_runtime_flags(self._h, ctypes.byref(fl)), "tlfea_get_runtime_flags")
         return fl.value
@@ -305,6 +319,8 @@ class TLBatch:
             pass
 
     def assemble(self, q, qdot, h, f=None, vals=None, loop: bool = False):
+        """f_int and h df/dq + df/dqdot of every body (h per body) in one graph-captured launch
+        pair, or through per-body calls with loop=True."""
         nd, nz = self.dof_off[-1], self.nnz_off[-1]
         f = torch.empty(nd, dtype=torch.float64, device=q.device) if f is None else f
         vals = torch.empty(nz, dtype=torch.float64, device=q.device) if vals is None else vals

@@ -548,6 +548,12 @@ static int coef_of(const orc_mesh* mesh, int e, int a) {
   return 4 * mesh->conn[npn * e + a / 4] + a % 4;
 }
 
+/* 1 if local shape function a carries a position (value) coefficient: every
+ * T10 node, and coefficient k = 0 of each ANCF node */
+static int is_position(const orc_mesh* mesh, int a) {
+  return mesh->elem_type == ORC_T10 ? 1 : (a % 4 == 0);
+}
+
 /* parent gradients of all shape functions at qp; returns n_en */
 static int parent_gradients(const orc_mesh* mesh, int e, const double* xi, double* dN) {
   if (mesh->elem_type == ORC_T10) {
@@ -632,13 +638,24 @@ static int element_int(const orc_mesh* mesh, const mat_int* mat, int e, const do
     double dV;
     int rc = qp_geometry(mesh, e, pts + 3 * qp, w[qp], &dV, g);
     if (rc != ORC_OK) return rc;
-    /* Hd = sum_a (x_a - X_a) (x) g_a, Fdot = sum_a xdot_a (x) g_a */
-    double Hd[9] = {0}, Fd[9] = {0};
+    /* Hd = sum_a (x_a - X_a) (x) g_a, Fdot = sum_a xdot_a (x) g_a.  The
+     * position shape functions sum to one, so their gradients sum to zero:
+     * taking the displacement and velocity of the element's first position
+     * coefficient out of every position coefficient leaves both sums unchanged,
+     * and keeps their terms of the size of the element's own deformation under
+     * a large rigid motion (otherwise |x - X| / h digits are lost). */
+    double Hd[9] = {0}, Fd[9] = {0}, u0[3], v0[3];
+    const int c0 = coef_of(mesh, e, 0);
+    for (int i = 0; i < 3; ++i) {
+      u0[i] = q[3 * c0 + i] - mesh->X[3 * c0 + i];
+      v0[i] = qdot ? qdot[3 * c0 + i] : 0.0;
+    }
     for (int a = 0; a < nen; ++a) {
       int c = coef_of(mesh, e, a);
+      const int pos = is_position(mesh, a);
       for (int i = 0; i < 3; ++i) {
-        double u = q[3 * c + i] - mesh->X[3 * c + i];
-        double v = qdot ? qdot[3 * c + i] : 0.0;
+        double u = q[3 * c + i] - mesh->X[3 * c + i] - (pos ? u0[i] : 0.0);
+        double v = (qdot ? qdot[3 * c + i] : 0.0) - (pos ? v0[i] : 0.0);
         for (int J = 0; J < 3; ++J) {
           Hd[3 * i + J] += u * g[3 * a + J];
           Fd[3 * i + J] += v * g[3 * a + J];
@@ -900,11 +917,16 @@ double orc_energy(const orc_mesh* mesh, const orc_material* mat, const double* q
     for (int qp = 0; qp < nq; ++qp) {
       double dV;
       if (qp_geometry(mesh, e, pts + 3 * qp, w[qp], &dV, g) != ORC_OK) return NAN;
+      /* the displacement gradient as in element_int (first position coefficient taken out) */
       double Hd[9] = {0};
+      const int c0 = coef_of(mesh, e, 0);
       for (int a = 0; a < nen; ++a) {
         int c = coef_of(mesh, e, a);
-        for (int i = 0; i < 3; ++i)
-          for (int J = 0; J < 3; ++J) Hd[3 * i + J] += (q[3 * c + i] - mesh->X[3 * c + i]) * g[3 * a + J];
+        const int pos = is_position(mesh, a);
+        for (int i = 0; i < 3; ++i) {
+          const double u = q[3 * c + i] - mesh->X[3 * c + i] - (pos ? q[3 * c0 + i] - mesh->X[3 * c0 + i] : 0.0);
+          for (int J = 0; J < 3; ++J) Hd[3 * i + J] += u * g[3 * a + J];
+        }
       }
       total += dV * energy_int(&mi, Hd);
     }

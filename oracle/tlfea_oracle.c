@@ -594,11 +594,18 @@ static int qp_geometry(const orc_mesh* mesh, int e, const double* xi, double wq,
   double dN[48];
   int nen = parent_gradients(mesh, e, xi, dN);
   if (nen < 0) return ORC_EDEGENERATE;
+  /* J0 = sum_a X_a (x) dN_a, with the first position coefficient taken out of
+   * every position coefficient (their parent gradients sum to zero): the same
+   * sum, with terms of the element's size however far it lies from the origin */
   double J0[9] = {0};
+  const double* X0 = mesh->X + 3 * coef_of(mesh, e, 0);
   for (int a = 0; a < nen; ++a) {
     const double* Xa = mesh->X + 3 * coef_of(mesh, e, a);
-    for (int i = 0; i < 3; ++i)
-      for (int m = 0; m < 3; ++m) J0[3 * i + m] += Xa[i] * dN[3 * a + m];
+    const int pos = is_position(mesh, a);
+    for (int i = 0; i < 3; ++i) {
+      const double xa = Xa[i] - (pos ? X0[i] : 0.0);
+      for (int m = 0; m < 3; ++m) J0[3 * i + m] += xa * dN[3 * a + m];
+    }
   }
   double Jinv[9];
   double det = inv3(J0, Jinv);

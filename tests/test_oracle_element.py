@@ -383,3 +383,59 @@ def test_vjp(orc, material):
         fdn, _ = orc.assemble(m, md_, q, qdot, want_K=False)
         fd = w @ (fu - fdn) / (2 * h)
         assert abs(gp[i] - fd) <= 1e-6 * abs(fd), (i, gp[i], fd)
+
+
+def _t10_force_extended(Xe, xe, lam, mu):
+    """SVK element force of one straight-sided T10 element in numpy's extended
+    precision (80-bit on x86), written from the textbook definitions: closed-form
+    quadratic shape-function gradients, Keast's 5-point rule, E from the
+    deformation gradient itself, S = lam tr(E) I + 2 mu E, f_a = sum_q P g_a dV."""
+    ld = np.longdouble
+    Xe, xe = Xe.astype(ld), xe.astype(ld)
+    sixth = ld(1) / ld(6)
+    pts = [(ld(0.25),) * 4] + [tuple(ld(0.5) if j == i else sixth for j in range(4)) for i in range(4)]
+    wts = [ld(-0.8) / 6] + [ld(0.45) / 6] * 4
+    dL = np.array([[-1, -1, -1], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=ld)
+    f = np.zeros((10, 3), dtype=ld)
+    for L, w in zip(pts, wts):
+        dN = np.zeros((10, 3), dtype=ld)
+        for c in range(4):
+            dN[c] = (4 * L[c] - 1) * dL[c]
+        for k, (c, d) in enumerate(W.T10_EDGES):
+            dN[4 + k] = 4 * (L[c] * dL[d] + L[d] * dL[c])
+        J0 = Xe.T @ dN  # sum_a X_a (x) dN_a
+        g = dN @ np.linalg.inv(J0.astype(np.float64)).astype(ld)
+        # refine the inverse once in extended precision (Newton step)
+        Jinv = np.linalg.inv(J0.astype(np.float64)).astype(ld)
+        Jinv = Jinv + Jinv @ (np.eye(3, dtype=ld) - J0 @ Jinv)
+        g = dN @ Jinv
+        F = xe.T @ g
+        E = (F.T @ F - np.eye(3, dtype=ld)) / 2
+        S = lam * np.trace(E) * np.eye(3, dtype=ld) + 2 * mu * E
+        det = J0[0, 0] * (J0[1, 1] * J0[2, 2] - J0[1, 2] * J0[2, 1]) - J0[0, 1] * (
+            J0[1, 0] * J0[2, 2] - J0[1, 2] * J0[2, 0]) + J0[0, 2] * (J0[1, 0] * J0[2, 1] - J0[1, 1] * J0[2, 0])
+        f += (g @ (F @ S).T) * (det * w)
+    return f.astype(np.float64).ravel()
+
+
+def test_large_rotation_small_strain_force_to_extended_precision(orc):
+    """Under a 1 rad rotation with a 1e-3 strain the element force is the
+    difference of O(1) terms; the oracle's FP64 force must match an
+    extended-precision evaluation of the same FP64 inputs to 1e-12 of its size
+    (the displacement gradient taken from element-relative values)."""
+    if np.finfo(np.longdouble).eps > 1e-18:
+        pytest.skip("numpy longdouble is not extended precision here")
+    E_, nu = 1e7, 0.3
+    lam, mu = E_ * nu / ((1 + nu) * (1 - 2 * nu)), E_ / (2 * (1 + nu))
+    wl = W.t10_rotated(4, 2, 2, 77, "rot", frac=1e-3, material=W.Material(W.SVK, (E_, nu, 0.0)))
+    om = orc.Mesh.of(wl.mesh)
+    omat = orc.material_of(wl.material)
+    X = wl.mesh.X
+    x = wl.q.reshape(-1, 3)
+    worst = 0.0
+    for e in range(0, wl.mesh.n_elem, 7):
+        ids = wl.mesh.conn[e]
+        fe, _ = orc.element(om, omat, e, wl.q, None, want_K=False)
+        fx = _t10_force_extended(X[ids], x[ids], lam, mu)
+        worst = max(worst, np.abs(fe - fx).max() / np.abs(fx).max())
+    assert worst <= 1e-12, worst

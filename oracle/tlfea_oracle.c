@@ -353,31 +353,57 @@ static void pk1_int(const mat_int* m, const double* Hd, const double* Fd, double
   kinematics(Hd, &k);
   const double* F = k.F;
   for (int i = 0; i < 9; ++i) P[i] = 0.0;
+  /* Green strain E = (C - I) / 2 = (Hd + Hd^T + Hd^T Hd) / 2: of the size of the
+   * strain, with no rounded O(1) term left in it when Hd itself is small */
+  double E[9], S[9], trE = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = Hd[3 * i + j] + Hd[3 * j + i];
+      for (int m2 = 0; m2 < 3; ++m2) s += Hd[3 * m2 + i] * Hd[3 * m2 + j];
+      E[3 * i + j] = 0.5 * s;
+    }
+  for (int i = 0; i < 3; ++i) trE += E[4 * i];
   if (m->kind == ORC_SVK) {
-    /* E = (Hd + Hd^T + Hd^T Hd) / 2, S = lambda tr(E) I + 2 mu E, P = F S */
-    double E[9], S[9], trE = 0;
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        double s = Hd[3 * i + j] + Hd[3 * j + i];
-        for (int m2 = 0; m2 < 3; ++m2) s += Hd[3 * m2 + i] * Hd[3 * m2 + j];
-        E[3 * i + j] = 0.5 * s;
-      }
-    for (int i = 0; i < 3; ++i) trE += E[4 * i];
+    /* S = lambda tr(E) I + 2 mu E, P = F S */
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) S[3 * i + j] = m->c0 * trE * kron(i, j) + 2.0 * m->c1 * E[3 * i + j];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j)
-        for (int m2 = 0; m2 < 3; ++m2) P[3 * i + j] += F[3 * i + m2] * S[3 * m2 + j];
   } else {
-    /* P = 2 mu10 J^-2/3 (F - I1/3 F^-T) + 2 mu01 J^-4/3 (I1 F - F C - 2/3 I2 F^-T)
-     *     + kappa J (J - 1) F^-T */
+    /* S = 2 dW/dC = 2 mu10 J^-2/3 (I - I1/3 C^-1) + 2 mu01 J^-4/3 (I1 I - C - 2/3 I2 C^-1)
+     *     + kappa J (J - 1) C^-1.
+     * With C = I + 2E the two brackets are C^-1 times
+     *   C - I1/3 I = 2 dev(E)   and
+     *   I1 C - C^2 - 2/3 I2 I = 2 dev(E) + 4 tr(E) E - 4 E^2 + 4/3 (E:E - tr(E)^2) I,
+     * so S is formed from E alone, without the difference of O(1) numbers that
+     * the first form takes at small strain. */
     double a = pow(k.J, -2.0 / 3.0), b = pow(k.J, -4.0 / 3.0);
-    for (int i = 0; i < 9; ++i) {
-      P[i] = 2.0 * m->c0 * a * (F[i] - k.I1 / 3.0 * k.G[i]) +
-             2.0 * m->c1 * b * (k.I1 * F[i] - k.FC[i] - 2.0 / 3.0 * k.I2 * k.G[i]) +
-             m->c2 * k.J * k.Jm1 * k.G[i];
-    }
+    double EE[9], ee = 0.0, T[9], C[9], Ci[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0;
+        for (int m2 = 0; m2 < 3; ++m2) s += E[3 * i + m2] * E[3 * m2 + j];
+        EE[3 * i + j] = s;
+        ee += E[3 * i + j] * E[3 * i + j];
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double dev = E[3 * i + j] - trE / 3.0 * kron(i, j);
+        double b1 = 2.0 * dev;
+        double b2 = 2.0 * dev + 4.0 * trE * E[3 * i + j] - 4.0 * EE[3 * i + j] +
+                    4.0 / 3.0 * (ee - trE * trE) * kron(i, j);
+        T[3 * i + j] = 2.0 * m->c0 * a * b1 + 2.0 * m->c1 * b * b2 + m->c2 * k.J * k.Jm1 * kron(i, j);
+        C[3 * i + j] = kron(i, j) + 2.0 * E[3 * i + j];
+      }
+    inv3(C, Ci);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0;
+        for (int m2 = 0; m2 < 3; ++m2) s += Ci[3 * i + m2] * T[3 * m2 + j];
+        S[3 * i + j] = s;
+      }
   }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int m2 = 0; m2 < 3; ++m2) P[3 * i + j] += F[3 * i + m2] * S[3 * m2 + j];
   if (m->eta != 0.0 || m->lam_v != 0.0) {
     /* Edot = (Fdot^T F + F^T Fdot) / 2, S_v = 2 eta Edot + lam_v tr(Edot) I, P_v = F S_v */
     double Ed[9], Sv[9], trEd = 0;

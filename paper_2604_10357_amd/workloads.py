@@ -330,3 +330,28 @@ def rotation_matrix(axis, angle):
     axis = axis / np.linalg.norm(axis)
     K = np.array([[0, -axis[2], axis[1]], [axis[2], 0, -axis[0]], [-axis[1], axis[0], 0]])
     return np.eye(3) + np.sin(angle) * K + (1.0 - np.cos(angle)) * (K @ K)
+
+
+def t10_rotated(nx, ny, nz, seed, name, angle=1.0, axis=(1.0, 2.0, 3.0), frac=1e-3,
+                vel_sigma=0.05, lx=1.0, ly=0.1, lz=0.1,
+                material: Optional[Material] = None) -> Workload:
+    """A T10 box beam deformed by small noise and then turned as a rigid body.
+
+    The reference box is [0,lx]x[0,ly]x[0,lz] with nx*ny*nz Kuhn cells; every
+    node (mid-edge nodes included) is moved by U(-frac*h_k, +frac*h_k) per axis,
+    which gives strains of order frac, and the perturbed body is rotated by
+    ``angle`` radians about ``axis`` through the origin.  Far from the origin
+    the rigid displacement is of the body's own size while the strain stays of
+    order frac: the regime of a beam that bends through a large rotation.
+    Velocities are N(0, vel_sigma^2) per DOF.  Draw order: position noise,
+    velocity noise, cotangent."""
+    rng = np.random.default_rng(seed)
+    mesh = kuhn_t10_box(nx, ny, nz, lx, ly, lz)
+    if material is None:
+        material = Material(MOONEY_RIVLIN, (MR_BASE["mu10"], MR_BASE["mu01"], MR_BASE["kappa"]),
+                            MR_BASE["eta"], MR_BASE["eta"])
+    q, qdot = _t10_perturbed(mesh, (lx / nx, ly / ny, lz / nz), rng, frac, vel_sigma)
+    R = rotation_matrix(axis, angle)
+    q = (q.reshape(-1, 3) @ R.T).ravel()
+    w = rng.normal(0.0, 1.0, size=q.shape[0])
+    return Workload(name, mesh, material, q, qdot, w)

@@ -177,3 +177,77 @@ def test_jm1_accurate_near_identity(orc):
     P = orc.pk1(m, Hd)
     jm1 = 2.5e-12  # to first order
     assert abs(P[0, 0] - jm1) <= 1e-9 * jm1
+
+
+def _pk1_extended(kind, c, Hd):
+    """First Piola-Kirchhoff stress in numpy's extended precision (80-bit on
+    x86) from the textbook forms in F: SVK  P = F (lam tr(E) I + 2 mu E) with
+    E = (F^T F - I)/2; Mooney-Rivlin
+    P = 2 mu10 J^-2/3 (F - I1/3 F^-T) + 2 mu01 J^-4/3 (I1 F - F C - 2/3 I2 F^-T)
+        + kappa J (J - 1) F^-T."""
+    ld = np.longdouble
+    F = np.eye(3, dtype=ld) + np.asarray(Hd, dtype=np.float64).astype(ld).reshape(3, 3)
+    C = F.T @ F
+    cof = np.array([[F[1, 1] * F[2, 2] - F[1, 2] * F[2, 1], F[1, 2] * F[2, 0] - F[1, 0] * F[2, 2],
+                     F[1, 0] * F[2, 1] - F[1, 1] * F[2, 0]],
+                    [F[0, 2] * F[2, 1] - F[0, 1] * F[2, 2], F[0, 0] * F[2, 2] - F[0, 2] * F[2, 0],
+                     F[0, 1] * F[2, 0] - F[0, 0] * F[2, 1]],
+                    [F[0, 1] * F[1, 2] - F[0, 2] * F[1, 1], F[0, 2] * F[1, 0] - F[0, 0] * F[1, 2],
+                     F[0, 0] * F[1, 1] - F[0, 1] * F[1, 0]]], dtype=ld)
+    J = (F[0] * cof[0]).sum()
+    G = cof / J  # F^-T
+    if kind == "svk":
+        lam, mu = c
+        E = (C - np.eye(3, dtype=ld)) / 2
+        return F @ (lam * np.trace(E) * np.eye(3, dtype=ld) + 2 * mu * E)
+    mu10, mu01, kap = (ld(x) for x in c)
+    I1 = np.trace(C)
+    I2 = (I1 * I1 - np.trace(C @ C)) / 2
+    a = J ** (ld(-2) / 3)
+    return (2 * mu10 * a * (F - I1 / 3 * G) + 2 * mu01 * a * a * (I1 * F - F @ C - ld(2) / 3 * I2 * G)
+            + kap * J * (J - 1) * G)
+
+
+@pytest.mark.parametrize("kappa_over_mu", [400.0, 10.0])
+@pytest.mark.parametrize("strain", [1e-2, 1e-4])
+def test_mr_stress_at_small_strain_to_extended_precision(orc, kappa_over_mu, strain):
+    """At small strain the textbook Mooney-Rivlin stress is a difference of O(1)
+    numbers; the oracle writes S in the Green strain instead.  Both are the same
+    function: the oracle's FP64 stress must match the textbook form evaluated in
+    extended precision on the same FP64 input to 1e-13 of its size (a dropped
+    or mis-signed term in the strain form shows at strain 1e-2 as an error of
+    order the strain itself)."""
+    if np.finfo(np.longdouble).eps > 1e-18:
+        pytest.skip("numpy longdouble is not extended precision here")
+    mu10, mu01 = 2e5, 5e4
+    c = (mu10, mu01, kappa_over_mu * 2 * (mu10 + mu01))
+    m = orc.material(orc.MR, c)
+    rng = np.random.default_rng(12)
+    for _ in range(50):
+        Hd = rng.uniform(-strain, strain, size=(3, 3))
+        P = orc.pk1(m, Hd)
+        Px = _pk1_extended("mr", c, Hd).astype(np.float64)
+        assert np.abs(P - Px).max() <= 1e-13 * np.abs(Px).max(), (np.abs(P - Px).max() / np.abs(Px).max())
+
+
+@pytest.mark.parametrize("name", ["svk", "mr"])
+def test_stress_under_large_rotation_to_extended_precision(orc, name):
+    """A 1 rad rotation of a 1e-3 strain: the oracle's stress must match the
+    extended-precision textbook form on the same input to within the rounding
+    that the O(1) entries of Hd themselves allow (a few eps over the strain)."""
+    if np.finfo(np.longdouble).eps > 1e-18:
+        pytest.skip("numpy longdouble is not extended precision here")
+    from paper_2604_10357_amd import workloads as W
+    E_, nu = SVK_P
+    c = (E_ * nu / ((1 + nu) * (1 - 2 * nu)), E_ / (2 * (1 + nu))) if name == "svk" else (2e5, 5e4, 1e8)
+    m = orc.material(orc.SVK, SVK_P) if name == "svk" else orc.material(orc.MR, c)
+    R = W.rotation_matrix((1.0, 2.0, 3.0), 1.0)
+    rng = np.random.default_rng(13)
+    for _ in range(50):
+        eps = rng.uniform(-1e-3, 1e-3, size=(3, 3))
+        Hd = R @ (np.eye(3) + eps) - np.eye(3)
+        P = orc.pk1(m, Hd)
+        Px = _pk1_extended(name, c, Hd).astype(np.float64)
+        # scale: the size of the stress a 1e-3 strain produces in this material
+        scale = np.abs(Px).max() if name == "svk" else max(np.abs(Px).max(), c[2] * 1e-3)
+        assert np.abs(P - Px).max() <= 1e-11 * scale, np.abs(P - Px).max() / scale

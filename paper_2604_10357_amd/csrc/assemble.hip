@@ -144,6 +144,11 @@ __device__ __forceinline__ void gather_nodal(const AsmArgs& a, int64_t e_lo, int
 // Displacement and velocity gradients at point q of element e from its nodal
 // values in LDS (ne: 6 doubles per coefficient): Hd = sum_a u_a (x) g_a,
 // Fd = sum_a qdot_a (x) g_a, with g_a = J0^-T dN_a (Sec. 4.3, Eq. F_assembly).
+// The position functions sum to one, so their gradients sum to zero and the
+// first coefficient's values may be taken out of every position coefficient:
+// the terms then stay of the size of the element's own deformation instead of
+// its rigid displacement (a body turned far from the origin keeps the digits
+// of its strain).
 // PART: coefficients in steps of TLFEA_KIN_UNROLL instead of all at once (a
 // full unroll keeps every table load in flight; for the shell's 16
 // coefficients that caps the kernels at one wave per SIMD).  Measured per
@@ -156,15 +161,19 @@ __device__ __forceinline__ void tile_kinematics(const AsmArgs& a, const double* 
   double sc[4];
   load_geometry<Rule>(a, e, q, Jinv, det);
   element_scales<Rule>(a, e, sc);
-  double Du[9], Dv[9];
+  double Du[9], Dv[9], r0[6];
 #pragma unroll
   for (int t = 0; t < 9; ++t) Du[t] = Dv[t] = 0.0;
+#pragma unroll
+  for (int t = 0; t < 6; ++t) r0[t] = ne[t];
   auto add = [&](int al) __attribute__((always_inline)) {
     const double s = sc[al % 4];
     const double w0 = Rule::dN_rt(q, al, 0) * s, w1 = Rule::dN_rt(q, al, 1) * s, w2 = Rule::dN_rt(q, al, 2) * s;
+    const bool position = Rule::MC == 1 || (al & 3) == 0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const double u = ne[6 * al + i], v = ne[6 * al + 3 + i];
+      const double u = ne[6 * al + i] - (position ? r0[i] : 0.0);
+      const double v = ne[6 * al + 3 + i] - (position ? r0[3 + i] : 0.0);
       Du[3 * i] += u * w0;
       Du[3 * i + 1] += u * w1;
       Du[3 * i + 2] += u * w2;

@@ -45,23 +45,32 @@ __device__ __forceinline__ void load_geometry(const AsmArgs& a, int64_t ge, int 
 
 // Gradient  sum_a (u_a - X_a) (x) g_a  (X may be null) of a nodal field u at point q.
 // Formed as (sum_a u_a (x) dN_a) J0^-1: parent gradient first, then one 3x3 product.
+// The gradients of the position functions sum to zero, so the value at the
+// element's first coefficient is taken out of every position coefficient: the
+// terms stay of the size of the element's own variation of the field.
 template <class Rule>
 __device__ __forceinline__ void field_gradient(const AsmArgs& a, int64_t ge, int q, const double* sc,
                                                const double* u, const double* X, const double* Jinv,
                                                double* out) {
   const int32_t* conn_e = a.conn + ge * Rule::NPN;
-  double D[9];
+  double D[9], r0[3];
 #pragma unroll
   for (int t = 0; t < 9; ++t) D[t] = 0.0;
+  {
+    const int64_t c0 = coef_of<Rule>(conn_e, 0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r0[i] = X ? u[3 * c0 + i] - X[3 * c0 + i] : u[3 * c0 + i];
+  }
 #pragma unroll
   for (int al = 0; al < Rule::NEN; ++al) {
     const int64_t c = coef_of<Rule>(conn_e, al);
     const double s = sc[al % 4];
     const double w0 = Rule::dN_rt(q, al, 0) * s, w1 = Rule::dN_rt(q, al, 1) * s,
                  w2 = Rule::dN_rt(q, al, 2) * s;
+    const bool position = Rule::MC == 1 || (al & 3) == 0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const double d = X ? u[3 * c + i] - X[3 * c + i] : u[3 * c + i];
+      const double d = (X ? u[3 * c + i] - X[3 * c + i] : u[3 * c + i]) - (position ? r0[i] : 0.0);
       D[3 * i] += d * w0;
       D[3 * i + 1] += d * w1;
       D[3 * i + 2] += d * w2;

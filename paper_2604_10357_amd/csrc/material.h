@@ -13,11 +13,22 @@
 // whose 3x3 factors are formed once per point; each of the 81 entries then
 // costs a handful of FMAs.
 //
-// Precision: the displacement gradient Hd = F - I arrives in float64.  J - 1 is
-// formed in float64 from the invariants of Hd (no cancellation near J = 1),
-// and J^-2/3, J^-4/3 and the volumetric coefficients kappa J (J-1),
-// kappa J (2J-1) stay float64.  Everything else runs in R (float64 for the
-// FP64 path, float32 for the mixed path).
+// Precision: the displacement gradient Hd = F - I arrives in float64.  The
+// Green strain E = (Hd + Hd^T + Hd^T Hd) / 2 is formed from it in float64,
+// so it carries no rounded O(1) term even when the strain is small and the
+// element has turned through a large rotation; J - 1 is formed in float64 from
+// the invariants of Hd (no cancellation near J = 1), and J^-2/3, J^-4/3 and the
+// volumetric coefficients kappa J (J-1), kappa J (2J-1) stay float64.  The
+// stresses are written in E alone:
+//   SVK : S = lambda tr(E) I + 2 mu E,                       P = F S
+//   MR  : S = 2 dW/dC = C^-1 T with C = I + 2E and
+//         T = 2 mu10 J^-2/3 (2 dev E)
+//           + 2 mu01 J^-4/3 (2 dev E + 4 tr(E) E - 4 E^2 + 4/3 (E:E - tr(E)^2) I)
+//           + kappa J (J - 1) I,                             P = F C^-1 T = F^-T T
+// (the two brackets are C - I1/3 I and I1 C - C^2 - 2/3 I2 I rewritten with
+// C = I + 2E), so no stress is a difference of O(1) numbers.  Everything after
+// the cast of E runs in R (float64 for the FP64 path, float32 for the mixed
+// path); the tangent factors are O(1) combinations and are formed from F in R.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -61,14 +72,24 @@ __device__ __forceinline__ unsigned point_update(const MatParams& mp, const doub
                                                  const double* Fd64, double dV, double alpha,
                                                  double beta, PointOut<R>& o) {
   unsigned flags = 0;
-  R Fd[9], H[9];
+  R Fd[9], E[9];
   R* F = o.F;
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
-    H[t] = (R)Hd[t];
-    F[t] = H[t] + ((t % 4) == 0 ? R(1) : R(0));
+    F[t] = (R)Hd[t] + ((t % 4) == 0 ? R(1) : R(0));
     Fd[t] = (R)Fd64[t];
   }
+  // Green strain in float64, then cast
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      const double e = 0.5 * (Hd[3 * i + j] + Hd[3 * j + i] + Hd[i] * Hd[j] + Hd[3 + i] * Hd[3 + j] +
+                              Hd[6 + i] * Hd[6 + j]);
+      E[3 * i + j] = (R)e;
+      E[3 * j + i] = (R)e;
+    }
+  const R trE = E[0] + E[4] + E[8];
   const bool kv = (mp.eta != 0.0) || (mp.lam_v != 0.0);
   const R a_ = (R)alpha, b_ = (R)beta, sdv = (R)dV;
   R S[9];  // total second Piola-Kirchhoff stress of the S-type terms (SVK + KV)
@@ -81,11 +102,13 @@ __device__ __forceinline__ unsigned point_update(const MatParams& mp, const doub
     o.Y[t] = R(0);
   }
   R B[9];  // F F^T
+  if (WANT_A) {
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-      B[3 * i + j] = F[3 * i] * F[3 * j] + F[3 * i + 1] * F[3 * j + 1] + F[3 * i + 2] * F[3 * j + 2];
+      for (int j = 0; j < 3; ++j)
+        B[3 * i + j] = F[3 * i] * F[3 * j] + F[3 * i + 1] * F[3 * j + 1] + F[3 * i + 2] * F[3 * j + 2];
+  }
 
   double jm1 = jm1_of(Hd);
   double J = 1.0 + jm1;
@@ -93,16 +116,11 @@ __device__ __forceinline__ unsigned point_update(const MatParams& mp, const doub
 
   o.mr = (mp.kind == 2);
   R Pel[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) Pel[t] = R(0);
   if (mp.kind == 1) {
-    // SVK: E = (H + H^T + H^T H) / 2
+    // SVK
     const R lam = (R)mp.c0, mu = (R)mp.c1;
-    R E[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-        E[3 * i + j] = R(0.5) * (H[3 * i + j] + H[3 * j + i] + H[i] * H[j] + H[3 + i] * H[3 + j] + H[6 + i] * H[6 + j]);
-    R trE = E[0] + E[4] + E[8];
 #pragma unroll
     for (int t = 0; t < 9; ++t) S[t] = R(2) * mu * E[t] + ((t % 4) == 0 ? lam * trE : R(0));
     if (WANT_A) {
@@ -114,30 +132,11 @@ __device__ __forceinline__ unsigned point_update(const MatParams& mp, const doub
         o.Y[t] = a_ * mu * F[t];
       }
     }
-#pragma unroll
-    for (int t = 0; t < 9; ++t) Pel[t] = R(0);
   } else {
     // Mooney-Rivlin with decoupled invariants and (kappa/2)(J-1)^2
     const double cbJ = cbrt(J);
     const double a = 1.0 / (cbJ * cbJ);  // J^-2/3
     const double b = a * a;              // J^-4/3
-    R C[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-        C[3 * i + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
-    R FC[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-        FC[3 * i + j] = F[3 * i] * C[j] + F[3 * i + 1] * C[3 + j] + F[3 * i + 2] * C[6 + j];
-    const R I1 = C[0] + C[4] + C[8];
-    R trC2 = R(0);
-#pragma unroll
-    for (int t = 0; t < 9; ++t) trC2 += C[t] * C[t];
-    const R I2 = R(0.5) * (I1 * I1 - trC2);
     // G = F^-T = cof(F) / J
     const R invJ = (R)(1.0 / J);
     R* G = o.G;
@@ -151,15 +150,52 @@ __device__ __forceinline__ unsigned point_update(const MatParams& mp, const doub
     G[7] = (F[2] * F[3] - F[0] * F[5]) * invJ;
     G[8] = (F[0] * F[4] - F[1] * F[3]) * invJ;
     const double mu10 = mp.c0, mu01 = mp.c1, kap = mp.c2;
-    const double I1d = (double)I1, I2d = (double)I2;
-    const double vol1 = kap * J * jm1;          // kappa J (J - 1)
-    const double vol2 = kap * J * (2.0 * J - 1.0);  // kappa J (2J - 1)
-    const R p1 = (R)(2.0 * mu10 * a), p2 = (R)(2.0 * mu01 * b), pv = (R)vol1;
-    const R i1third = I1 / R(3), i2two3 = R(2) / R(3) * I2;
+    const double vol1 = kap * J * jm1;  // kappa J (J - 1)
+    {
+      // T (symmetric) from E, then P_el = G T
+      R EE[9], ee = R(0);
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
-      Pel[t] = p1 * (F[t] - i1third * G[t]) + p2 * (I1 * F[t] - FC[t] - i2two3 * G[t]) + pv * G[t];
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          EE[3 * i + j] = E[3 * i] * E[j] + E[3 * i + 1] * E[3 + j] + E[3 * i + 2] * E[6 + j];
+          ee += E[3 * i + j] * E[3 * i + j];
+        }
+      const R p1 = (R)(2.0 * mu10 * a), p2 = (R)(2.0 * mu01 * b), pv = (R)vol1;
+      const R tr3 = trE / R(3), diag2 = R(4) / R(3) * (ee - trE * trE);
+      R T[9];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const R dev2 = R(2) * (E[t] - ((t % 4) == 0 ? tr3 : R(0)));
+        T[t] = p1 * dev2 + p2 * (dev2 + R(4) * trE * E[t] - R(4) * EE[t] + ((t % 4) == 0 ? diag2 : R(0))) +
+               ((t % 4) == 0 ? pv : R(0));
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          Pel[3 * i + j] = G[3 * i] * T[j] + G[3 * i + 1] * T[3 + j] + G[3 * i + 2] * T[6 + j];
+    }
     if (WANT_A) {
+      R C[9];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          C[3 * i + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
+      R FC[9];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          FC[3 * i + j] = F[3 * i] * C[j] + F[3 * i + 1] * C[3 + j] + F[3 * i + 2] * C[6 + j];
+      const R I1 = C[0] + C[4] + C[8];
+      R trC2 = R(0);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) trC2 += C[t] * C[t];
+      const R I2 = R(0.5) * (I1 * I1 - trC2);
+      const double I1d = (double)I1, I2d = (double)I2;
+      const double vol2 = kap * J * (2.0 * J - 1.0);  // kappa J (2J - 1)
       const R cdd = (R)(alpha * (2.0 * mu10 * a + 2.0 * mu01 * b * I1d));
       const R cmc = (R)(alpha * (-2.0 * mu01 * b));
       const R cfg = (R)(alpha * (-4.0 / 3.0 * mu10 * a - 8.0 / 3.0 * mu01 * b * I1d));
@@ -214,7 +250,7 @@ __device__ __forceinline__ unsigned point_update(const MatParams& mp, const doub
       }
     }
   }
-  // P = Pel + F S  (S holds the SVK stress and/or the viscous stress)
+  // P = Pel + F S  (Pel: the Mooney-Rivlin stress; S: the SVK and/or viscous stress)
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll

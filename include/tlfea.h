@@ -175,6 +175,26 @@ int tlfea_get_slot_map(tlfea_mesh_t mesh, int64_t elem_begin, int64_t elem_count
 int tlfea_internal_force(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double* d_f,
                          void* stream);
 
+/* Allocation-free form of tlfea_internal_force, for callers that cannot
+ * allocate or free device memory during a call: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same kernels, same
+ * fixed summation order and therefore the same bits as tlfea_internal_force
+ * on the same mesh and inputs; needs the pattern (TLFEA_ERR_NO_PATTERN
+ * before).  Instead of the mesh's work buffer, the per-incidence force blocks
+ * (n_elem * nodes per element * 3 * mc values: 4 bytes each in mixed
+ * precision, 8 in float64) go to a work area compiled into the library,
+ * TLFEA_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs on
+ * holds until the process ends.  A mesh whose blocks exceed it is rejected
+ * with TLFEA_ERR_TOO_LARGE before any work is enqueued (T10: up to 559,240
+ * elements in mixed precision, 279,620 in float64).  Every block is written
+ * before it is read, so the area needs no clearing between calls.  All calls
+ * on one GPU share that GPU's area: calls that overlap in time on one GPU
+ * (two streams, two host threads, two meshes) race and must be serialised by
+ * the caller.  The call allocates nothing and frees nothing. */
+#define TLFEA_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int tlfea_internal_force_noalloc(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double* d_f,
+                                 void* stream);
+
 /* CSR values of h * df/dq + df/dqdot = d f_int(q_n + h v, v) / dv -> d_vals (nnz). */
 int tlfea_tangent(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double h,
                   double* d_vals, void* stream);

@@ -25,7 +25,7 @@ TLFEA_FLAG_NONFINITE = 2
 EXPORTED = [
     "tlfea_status_string", "tlfea_version", "tlfea_mesh_create", "tlfea_mesh_destroy", "tlfea_mesh_info",
     "tlfea_mesh_set_material", "tlfea_mesh_set_precision", "tlfea_build_csr_pattern", "tlfea_get_csr_pattern",
-    "tlfea_get_slot_map", "tlfea_internal_force", "tlfea_tangent", "tlfea_tangent_ex", "tlfea_assemble",
+    "tlfea_get_slot_map", "tlfea_internal_force", "tlfea_internal_force_noalloc", "tlfea_tangent", "tlfea_tangent_ex", "tlfea_assemble",
     "tlfea_assemble_ex", "tlfea_assemble_accumulate", "tlfea_assemble_points", "tlfea_assemble_nodes", "tlfea_internal_force_vjp", "tlfea_get_runtime_flags", "tlfea_batch_create",
     "tlfea_batch_destroy", "tlfea_batch_offsets", "tlfea_batch_assemble", "tlfea_batch_assemble_loop",
     "tlfea_mesh_set_gather_shape", "tlfea_mesh_get_gather_shape", "tlfea_mesh_autotune",
@@ -97,6 +97,7 @@ def lib() -> ctypes.CDLL:
         "tlfea_get_csr_pattern": ([vp, vp, vp, i32, vp], ctypes.c_int),
         "tlfea_get_slot_map": ([vp, i64, i64, vp, i32, vp], ctypes.c_int),
         "tlfea_internal_force": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "tlfea_internal_force_noalloc": ([vp, vp, vp, vp, vp], ctypes.c_int),
         "tlfea_tangent": ([vp, vp, vp, dbl, vp, vp], ctypes.c_int),
         "tlfea_tangent_ex": ([vp, vp, vp, dbl, dbl, vp, vp], ctypes.c_int),
         "tlfea_assemble": ([vp, vp, vp, dbl, vp, vp, vp], ctypes.c_int),

@@ -136,6 +136,17 @@ class TLMesh:
                                              _ptr(out, n=self.n_dof), _stream()), "tlfea_internal_force")
         return out
 
+    def internal_force_noalloc(self, q, qdot=None, out=None):
+        """f_int(q, qdot) through the allocation-free entry point (the library
+        allocates nothing; its fixed per-GPU work area is shared by every such
+        call on the GPU, so overlapping calls race).  ``out`` is required."""
+        if out is None:
+            raise ValueError("internal_force_noalloc needs a caller-allocated output")
+        N.check(N.lib().tlfea_internal_force_noalloc(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof),
+                                                     _ptr(out, n=self.n_dof), _stream()),
+                "tlfea_internal_force_noalloc")
+        return out
+
     def tangent(self, q, qdot=None, h: float = 1.0, out=None, alpha=None, beta=None):
         """CSR values of alpha df/dq + beta df/dqdot, (alpha, beta) = (h, 1) unless given."""
         out = torch.empty(self.nnz, dtype=torch.float64, device=q.device) if out is None else out

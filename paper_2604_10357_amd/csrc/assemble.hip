@@ -37,6 +37,9 @@
 
 #include "kernel_common.h"
 
+// work area of the allocation-free force call, one copy per device
+static __device__ __align__(256) unsigned char scratch[TLFEA_NOALLOC_SCRATCH_BYTES];
+
 namespace tlfea {
 namespace {
 
@@ -1259,34 +1262,34 @@ __global__ __launch_bounds__(256) void k_force_sum(const int32_t* __restrict__ i
 int grid_of(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 template <class Rule, typename R>
-int launch_force_rule(const Mesh& m, const AsmArgs& a, hipStream_t s) {
+int launch_force_rule(const Mesh& m, const AsmArgs& a, void* blk, hipStream_t s) {
   constexpr int EB = force_elems<Rule>();
   const int64_t blocks = (m.n_elem + EB - 1) / EB;
   if (blocks > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
   if (blocks > 0)
     hipLaunchKernelGGL((k_elem_force<Rule, R>), dim3((unsigned)blocks), dim3(kForceThreads), 0, s, a, m.d_incpos,
-                       (R*)m.d_stage);
+                       (R*)blk);
   TLFEA_HIP_CHECK(hipGetLastError());
   return TLFEA_OK;
 }
 
 template <typename R>
-int launch_force_prec(const Mesh& m, const AsmArgs& a, hipStream_t s) {
-  if (m.elem_type == TLFEA_T10) return launch_force_rule<RuleT10, R>(m, a, s);
-  if (m.elem_type == TLFEA_ANCF3243) return launch_force_rule<RuleBeam, R>(m, a, s);
-  if (m.gl[0] == 3) return launch_force_rule<RuleAncf<3, 3, 2>, R>(m, a, s);
-  return launch_force_rule<RuleAncf<4, 4, 3>, R>(m, a, s);
+int launch_force_prec(const Mesh& m, const AsmArgs& a, void* blk, hipStream_t s) {
+  if (m.elem_type == TLFEA_T10) return launch_force_rule<RuleT10, R>(m, a, blk, s);
+  if (m.elem_type == TLFEA_ANCF3243) return launch_force_rule<RuleBeam, R>(m, a, blk, s);
+  if (m.gl[0] == 3) return launch_force_rule<RuleAncf<3, 3, 2>, R>(m, a, blk, s);
+  return launch_force_rule<RuleAncf<4, 4, 3>, R>(m, a, blk, s);
 }
 
-int launch_force_sum(const Mesh& m, double* f, bool accum, hipStream_t s) {
+int launch_force_sum(const Mesh& m, const void* blk, double* f, bool accum, hipStream_t s) {
   const int rpn = 3 * m.mc;
   if (m.n_dof > 0) {
     if (m.precision == TLFEA_MIXED)
       hipLaunchKernelGGL(k_force_sum<float>, dim3(grid_of(m.n_dof, 256)), dim3(256), 0, s, m.d_inc_off,
-                         (const float*)m.d_stage, m.n_dof, rpn, accum, f);
+                         (const float*)blk, m.n_dof, rpn, accum, f);
     else
       hipLaunchKernelGGL(k_force_sum<double>, dim3(grid_of(m.n_dof, 256)), dim3(256), 0, s, m.d_inc_off,
-                         (const double*)m.d_stage, m.n_dof, rpn, accum, f);
+                         (const double*)blk, m.n_dof, rpn, accum, f);
   }
   TLFEA_HIP_CHECK(hipGetLastError());
   return TLFEA_OK;
@@ -1550,7 +1553,8 @@ int launch_zero(double* p, int64_t n, hipStream_t s) {
 
 int launch_points(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s) {
   if (use_force_blocks(m, want_k))
-    return m.precision == TLFEA_MIXED ? launch_force_prec<float>(m, a, s) : launch_force_prec<double>(m, a, s);
+    return m.precision == TLFEA_MIXED ? launch_force_prec<float>(m, a, m.d_stage, s)
+                                     : launch_force_prec<double>(m, a, m.d_stage, s);
   if (use_rows(m, want_k) && m.elem_type != TLFEA_T10) {
     if (m.elem_type == TLFEA_ANCF3243) return launch_rows_mc_points<RuleBeam>(m, a, s);
     if (m.gl[0] == 3) return launch_rows_mc_points<RuleAncf<3, 3, 2>>(m, a, s);
@@ -1581,9 +1585,45 @@ int launch_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStream_t
     return m.gl[0] == 3 ? launch_rows_mc_nodes<RuleAncf<3, 3, 2>>(m, f, vals, accum, s, mt)
                         : launch_rows_mc_nodes<RuleAncf<4, 4, 3>>(m, f, vals, accum, s, mt);
   if (m.staged == 3) return launch_rows_nodes(m, f, vals, accum, s, mt);
-  if (m.staged == 4) return vals ? TLFEA_ERR_INVALID : launch_force_sum(m, f, accum, s);
+  if (m.staged == 4) return vals ? TLFEA_ERR_INVALID : launch_force_sum(m, m.d_stage, f, accum, s);
   if (m.precision == TLFEA_MIXED) return launch_nodes_prec<float>(m, f, vals, accum, s, mt);
   return launch_nodes_prec<double>(m, f, vals, accum, s, mt);
+}
+
+// Fixed work area of the allocation-free force call: the force blocks of one
+// call (3 mc values per incidence).  The kernels take its device address,
+// looked up once per device with that device current; the array's name in
+// host code is only a host-side stand-in for the symbol.
+int noalloc_scratch(void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  int dev = 0;
+  TLFEA_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    TLFEA_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return TLFEA_ERR_HIP;
+    it = addr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return TLFEA_OK;
+}
+
+size_t noalloc_force_bytes(const Mesh& m) {
+  return (size_t)m.n_elem * m.n_pn * 3 * m.mc * (m.precision == TLFEA_MIXED ? sizeof(float) : sizeof(double));
+}
+
+int launch_force_noalloc(const Mesh& m, const AsmArgs& a, double* f, hipStream_t s) {
+  if (!m.d_incpos) return TLFEA_ERR_NO_PATTERN;
+  if (noalloc_force_bytes(m) > kNoallocScratchBytes) return TLFEA_ERR_TOO_LARGE;
+  void* blk = nullptr;
+  if (int rc = noalloc_scratch(&blk)) return rc;
+  // every incidence block is written by pass 1 before pass 2 reads it: nothing to clear
+  int rc = m.precision == TLFEA_MIXED ? launch_force_prec<float>(m, a, blk, s) : launch_force_prec<double>(m, a, blk, s);
+  if (rc) return rc;
+  return launch_force_sum(m, blk, f, false, s);
 }
 
 int launch_force_gather_f64(const Mesh& m, const double* records, double* out, hipStream_t s) {

@@ -292,7 +292,8 @@ TLFEA_API const char* tlfea_status_string(int status) {
     case TLFEA_ERR_HIP: return "HIP runtime error";
     case TLFEA_ERR_NOMEM: return "device out of memory";
     case TLFEA_ERR_NO_PATTERN: return "CSR pattern not built";
-    case TLFEA_ERR_TOO_LARGE: return "size exceeds int32 indexing";
+    case TLFEA_ERR_TOO_LARGE:
+      return "size exceeds int32 indexing, or the fixed work area of an allocation-free call";
     default: return "unknown status";
   }
 }
@@ -533,6 +534,17 @@ TLFEA_API int tlfea_internal_force(tlfea_mesh_t mesh, const double* d_q, const d
                                    void* stream) {
   if (!d_f) return TLFEA_ERR_INVALID;
   return run_assembly(mesh, d_q, d_qdot, 1.0, 0.0, d_f, nullptr, stream);
+}
+
+TLFEA_API int tlfea_internal_force_noalloc(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double* d_f,
+                                           void* stream) {
+  int rc = tlfea::check_call(mesh, d_q, true);
+  if (rc) return rc;
+  if (!d_f) return TLFEA_ERR_INVALID;
+  Mesh& m = mesh->m;
+  m.last_stream = (hipStream_t)stream;
+  tlfea::AsmArgs a = tlfea::make_args(m, d_q, d_qdot, nullptr, nullptr, 1.0, 0.0);
+  return tlfea::launch_force_noalloc(m, a, d_f, (hipStream_t)stream);
 }
 
 // A null values pointer stands for the empty output of a pattern without

@@ -116,91 +116,6 @@ __device__ __forceinline__ R record_value(const HatOut<R>& h) {
   }
 }
 
-// Nodal values of a workgroup's elements in LDS: 6 doubles per (element,
-// coefficient), u = q - X then qdot (zero without qdot), for elements
-// e_lo .. e_lo + ne - 1.
-template <class Rule>
-__device__ __forceinline__ void gather_nodal(const AsmArgs& a, int64_t e_lo, int ne, double* nod) {
-  constexpr int NEN = Rule::NEN, NPN = Rule::NPN;
-  for (int idx = threadIdx.x; idx < ne * NEN; idx += blockDim.x) {
-    const int le = idx / NEN, al = idx - le * NEN;
-    const int64_t e = e_lo + le;
-    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (e < a.n_elem) {
-      const int64_t c = coef_of<Rule>(a.conn + e * NPN, al);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) v[i] = a.q[3 * c + i] - a.X[3 * c + i];
-      if (a.qdot) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) v[3 + i] = a.qdot[3 * c + i];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 6; ++t) nod[6 * idx + t] = v[t];
-  }
-}
-
-#ifndef TLFEA_KIN_UNROLL
-#define TLFEA_KIN_UNROLL 4
-#endif
-
-// Displacement and velocity gradients at point q of element e from its nodal
-// values in LDS (ne: 6 doubles per coefficient): Hd = sum_a u_a (x) g_a,
-// Fd = sum_a qdot_a (x) g_a, with g_a = J0^-T dN_a (Sec. 4.3, Eq. F_assembly).
-// The position functions sum to one, so their gradients sum to zero and the
-// first coefficient's values may be taken out of every position coefficient:
-// the terms then stay of the size of the element's own deformation instead of
-// its rigid displacement (a body turned far from the origin keeps the digits
-// of its strain).
-// PART: coefficients in steps of TLFEA_KIN_UNROLL instead of all at once (a
-// full unroll keeps every table load in flight; for the shell's 16
-// coefficients that caps the kernels at one wave per SIMD).  Measured per
-// kernel: steps for the shell everywhere and for the T10 force kernel, a full
-// unroll for the T10 element rows and the beam.
-template <class Rule, bool PART = (Rule::NEN > 10)>
-__device__ __forceinline__ void tile_kinematics(const AsmArgs& a, const double* ne, int64_t e, int q,
-                                                double (&Jinv)[9], double& det, double (&Hd)[9], double (&Fd)[9]) {
-  constexpr int NEN = Rule::NEN;
-  double sc[4];
-  load_geometry<Rule>(a, e, q, Jinv, det);
-  element_scales<Rule>(a, e, sc);
-  double Du[9], Dv[9], r0[6];
-#pragma unroll
-  for (int t = 0; t < 9; ++t) Du[t] = Dv[t] = 0.0;
-#pragma unroll
-  for (int t = 0; t < 6; ++t) r0[t] = ne[t];
-  auto add = [&](int al) __attribute__((always_inline)) {
-    const double s = sc[al % 4];
-    const double w0 = Rule::dN_rt(q, al, 0) * s, w1 = Rule::dN_rt(q, al, 1) * s, w2 = Rule::dN_rt(q, al, 2) * s;
-    const bool position = Rule::MC == 1 || (al & 3) == 0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double u = ne[6 * al + i] - (position ? r0[i] : 0.0);
-      const double v = ne[6 * al + 3 + i] - (position ? r0[3 + i] : 0.0);
-      Du[3 * i] += u * w0;
-      Du[3 * i + 1] += u * w1;
-      Du[3 * i + 2] += u * w2;
-      Dv[3 * i] += v * w0;
-      Dv[3 * i + 1] += v * w1;
-      Dv[3 * i + 2] += v * w2;
-    }
-  };
-  if constexpr (PART) {
-#pragma unroll TLFEA_KIN_UNROLL
-    for (int al = 0; al < NEN; ++al) add(al);
-  } else {
-#pragma unroll
-    for (int al = 0; al < NEN; ++al) add(al);
-  }
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int J = 0; J < 3; ++J) {
-      Hd[3 * i + J] = Du[3 * i] * Jinv[J] + Du[3 * i + 1] * Jinv[3 + J] + Du[3 * i + 2] * Jinv[6 + J];
-      Fd[3 * i + J] = Dv[3 * i] * Jinv[J] + Dv[3 * i + 1] * Jinv[3 + J] + Dv[3 * i + 2] * Jinv[6 + J];
-    }
-}
-
 // Pass 1 with the tangent, one workgroup per 256 consecutive (element, point)
 // indices.  The nodal values of the workgroup's elements (u = q - X and qdot
 // per coefficient) are gathered into LDS once instead of once per point, and
@@ -1626,16 +1541,12 @@ int launch_force_noalloc(const Mesh& m, const AsmArgs& a, double* f, hipStream_t
   return launch_force_sum(m, blk, f, false, s);
 }
 
-int launch_force_gather_f64(const Mesh& m, const double* records, double* out, hipStream_t s) {
-  if (m.n_ranges == 0) return launch_zero(out, m.n_dof, s);
-  const GatherOptions none;
-  if (m.elem_type == TLFEA_T10)
-    return launch_nodes_rule<RuleT10, double>(m, records, out, nullptr, false, s, none, false);
-  if (m.elem_type == TLFEA_ANCF3243)
-    return launch_nodes_rule<RuleBeam, double>(m, records, out, nullptr, false, s, none, false);
-  if (m.gl[0] == 3)
-    return launch_nodes_rule<RuleAncf<3, 3, 2>, double>(m, records, out, nullptr, false, s, none, false);
-  return launch_nodes_rule<RuleAncf<4, 4, 3>, double>(m, records, out, nullptr, false, s, none, false);
+int launch_block_sum(const Mesh& m, const double* blk, double* out, hipStream_t s) {
+  if (m.n_dof > 0)
+    hipLaunchKernelGGL(k_force_sum<double>, dim3(grid_of(m.n_dof, 256)), dim3(256), 0, s, m.d_inc_off, blk, m.n_dof,
+                       3 * m.mc, false, out);
+  TLFEA_HIP_CHECK(hipGetLastError());
+  return TLFEA_OK;
 }
 
 int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tu, const BatchArgs& b,

@@ -275,6 +275,127 @@ __device__ __forceinline__ unsigned point_update(const MatParams& mp, const doub
   return flags;
 }
 
+// First Piola-Kirchhoff stress per unit value of each material constant, in
+// float64.  P is linear in every constant, P = sum_i theta_i P_i with theta =
+// (lambda, mu) for SVK or (mu10, mu01, kappa) for Mooney-Rivlin, then
+// (eta, lam_v) for Kelvin-Voigt; the parts follow the E-based forms of
+// point_update (parts of an absent law are zero).
+__device__ __forceinline__ void stress_parts(int kind, bool kv, const double* Hd, const double* Fd,
+                                             double (&Pp)[5][9]) {
+  double F[9], E[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) F[t] = Hd[t] + ((t % 4) == 0 ? 1.0 : 0.0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      E[3 * i + j] = 0.5 * (Hd[3 * i + j] + Hd[3 * j + i] + Hd[i] * Hd[j] + Hd[3 + i] * Hd[3 + j] + Hd[6 + i] * Hd[6 + j]);
+  const double trE = E[0] + E[4] + E[8];
+  double T[3][9];  // stress-like factors of the elastic parts: P_i = F T_i (SVK) or G T_i (MR)
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const bool d = (t % 4) == 0;
+    T[0][t] = T[1][t] = T[2][t] = 0.0;
+    if (kind == 1) {
+      T[0][t] = d ? trE : 0.0;  // per unit lambda
+      T[1][t] = 2.0 * E[t];     // per unit mu
+    }
+  }
+  double L[9];  // left factor: F (SVK) or G = F^-T (MR)
+#pragma unroll
+  for (int t = 0; t < 9; ++t) L[t] = F[t];
+  if (kind != 1) {
+    const double jm1 = jm1_of(Hd), J = 1.0 + jm1;
+    const double cbJ = cbrt(J), a = 1.0 / (cbJ * cbJ), b = a * a, invJ = 1.0 / J;
+    L[0] = (F[4] * F[8] - F[5] * F[7]) * invJ;
+    L[1] = (F[5] * F[6] - F[3] * F[8]) * invJ;
+    L[2] = (F[3] * F[7] - F[4] * F[6]) * invJ;
+    L[3] = (F[2] * F[7] - F[1] * F[8]) * invJ;
+    L[4] = (F[0] * F[8] - F[2] * F[6]) * invJ;
+    L[5] = (F[1] * F[6] - F[0] * F[7]) * invJ;
+    L[6] = (F[1] * F[5] - F[2] * F[4]) * invJ;
+    L[7] = (F[2] * F[3] - F[0] * F[5]) * invJ;
+    L[8] = (F[0] * F[4] - F[1] * F[3]) * invJ;
+    double EE[9], ee = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        EE[3 * i + j] = E[3 * i] * E[j] + E[3 * i + 1] * E[3 + j] + E[3 * i + 2] * E[6 + j];
+        ee += E[3 * i + j] * E[3 * i + j];
+      }
+    const double diag2 = 4.0 / 3.0 * (ee - trE * trE);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const bool d = (t % 4) == 0;
+      const double dev2 = 2.0 * (E[t] - (d ? trE / 3.0 : 0.0));
+      T[0][t] = 2.0 * a * dev2;
+      T[1][t] = 2.0 * b * (dev2 + 4.0 * trE * E[t] - 4.0 * EE[t] + (d ? diag2 : 0.0));
+      T[2][t] = d ? J * jm1 : 0.0;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        Pp[p][3 * i + j] = L[3 * i] * T[p][j] + L[3 * i + 1] * T[p][3 + j] + L[3 * i + 2] * T[p][6 + j];
+  if (kv) {
+    double Ed[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) s += Fd[3 * m + i] * F[3 * m + j] + F[3 * m + i] * Fd[3 * m + j];
+        Ed[3 * i + j] = 0.5 * s;
+      }
+    const double trEd = Ed[0] + Ed[4] + Ed[8];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        Pp[3][3 * i + j] = 2.0 * (F[3 * i] * Ed[j] + F[3 * i + 1] * Ed[3 + j] + F[3 * i + 2] * Ed[6 + j]);
+        Pp[4][3 * i + j] = F[3 * i + j] * trEd;
+      }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) Pp[3][t] = Pp[4][t] = 0.0;
+  }
+}
+
+// Z_kL = sum_iJ Wc_iJ dP_v,iJ / dFdot_kL: the viscous tangent of the rate
+// applied to a cotangent gradient, from
+//   dP_v,iJ / dFdot_kL = eta (F_iL F_kJ + (F F^T)_ik d_JL) + lam_v F_iJ F_kL
+// giving Z = eta (F Wc^T F + F F^T Wc) + lam_v (Wc : F) F.
+__device__ __forceinline__ void rate_cotangent(double eta, double lam_v, const double* Hd, const double* Wc,
+                                               double* Z) {
+  double F[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) F[t] = Hd[t] + ((t % 4) == 0 ? 1.0 : 0.0);
+  double WtF[9], FtW[9], wf = 0.0;  // Wc^T F and F^T Wc
+#pragma unroll
+  for (int J = 0; J < 3; ++J)
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+      WtF[3 * J + L] = Wc[J] * F[L] + Wc[3 + J] * F[3 + L] + Wc[6 + J] * F[6 + L];
+      FtW[3 * J + L] = F[J] * Wc[L] + F[3 + J] * Wc[3 + L] + F[6 + J] * Wc[6 + L];
+    }
+#pragma unroll
+  for (int t = 0; t < 9; ++t) wf += Wc[t] * F[t];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+      double z = lam_v * wf * F[3 * k + L];
+#pragma unroll
+      for (int J = 0; J < 3; ++J) z += eta * (F[3 * k + J] * WtF[3 * J + L] + F[3 * k + J] * FtW[3 * J + L]);
+      Z[3 * k + L] = z;
+    }
+}
+
 // Z_kL = sum_iJ Wc_iJ A_iJkL (the tangent applied to a cotangent gradient Wc
 // from the left), term by term from the factored form:
 //   d_ik M_JL      -> (Wc M)_kL          N_ik d_JL  -> (N^T Wc)_kL

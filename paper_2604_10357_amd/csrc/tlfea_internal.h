@@ -326,7 +326,9 @@ int precompute_geometry(Mesh& m);
 int ensure_stage(Mesh& m, size_t bytes);
 // pass 2 over float64 force-type records (Phat_ik at 4 i + k, 12 per point)
 // at `records`, written to `out` (n_dof); used by the VJP (assemble.hip)
-int launch_force_gather_f64(const Mesh& m, const double* records, double* out, hipStream_t s);
+// per-node sums, in incidence order, of float64 blocks of 3 mc values per
+// (element, node) incidence at the node-sorted incidence positions -> out (n_dof)
+int launch_block_sum(const Mesh& m, const double* blk, double* out, hipStream_t s);
 constexpr size_t kNoallocScratchBytes = TLFEA_NOALLOC_SCRATCH_BYTES;
 size_t noalloc_force_bytes(const Mesh& m);
 int launch_force_noalloc(const Mesh& m, const AsmArgs& a, double* f, hipStream_t s);

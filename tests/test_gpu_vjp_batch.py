@@ -27,6 +27,9 @@ def test_vjp_against_oracle(name, wl):
     omat = oracle.material_of(wl.material)
     gq_ref, gqd_ref, gp_ref = oracle.vjp(om, omat, wl.q, wl.qdot, wl.w)
     gq, gqd, gp = m.vjp(cuda(wl.q), cuda(wl.qdot), cuda(wl.w))
+    # fixed-order sums: a second call gives the same bits
+    gq2, gqd2, gp2 = m.vjp(cuda(wl.q), cuda(wl.qdot), cuda(wl.w))
+    assert torch.equal(gq, gq2) and torch.equal(gqd, gqd2) and torch.equal(gp, gp2)
     assert rel_err(gq.cpu().numpy(), gq_ref)[0] <= 1e-12
     if np.abs(gqd_ref).max() > 0:
         assert rel_err(gqd.cpu().numpy(), gqd_ref)[0] <= 1e-12

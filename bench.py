@@ -64,6 +64,22 @@ def algorithmic_bytes(n_el, n_dof, nnz, n_pn=10, geo_bytes=80, extra_per_elem=0,
     return b
 
 
+def method_bytes(wl, nnz):
+    """Algorithmic bytes of one fused f + K call, counted on the method's own
+    data (the roofline's figure): K values written once (8 nnz), f
+    written (8 n_dof), q and qdot read (16 n_dof), connectivity (4 m per element,
+    m pattern nodes), reference geometry (80 B per affine T10, 80 B per point for
+    ANCF: J0^-1 and det J0) and a 4-byte block slot map (4 n_en^2 per element,
+    n_en shape functions).  Config 5: 1,650.9 MB = 3,439 B per element."""
+    m = wl.mesh
+    if m.elem_type == 1:
+        n_pn, geo, n_en = 10, 80, 10
+    else:
+        n_pn, n_en = m.conn.shape[1], (16 if m.elem_type == 2 else 8)
+        geo = 80 * int(np.prod(m.gl)) if m.elem_type == 2 else 80 * 12
+    return 8 * nnz + 24 * m.n_dof + m.n_elem * (4 * n_pn + geo + 4 * n_en * n_en)
+
+
 def mesh_bytes(wl, nnz, affine=True):
     m = wl.mesh
     if m.elem_type == 1:  # T10
@@ -147,13 +163,19 @@ def cpu_baseline(wl, f_gpu, vals_gpu, ro, cols, h, budget_s=12.0):
     errs = {}
     ef = np.abs(f_gpu[rows] - f_ref[rows]).max() / np.abs(f_ref[rows]).max()
     ro_s, cols_s = pat
-    kd, kmax = 0.0, 0.0
-    for r in rows[:: max(1, len(rows) // 3000)]:
-        a, b = ro_s[r], ro_s[r + 1]
-        ga, gb = ro[r], ro[r + 1]
-        assert np.array_equal(cols_s[a:b], cols[ga:gb])
-        kd = max(kd, np.abs(vals_gpu[ga:gb] - v_ref[a:b]).max())
-        kmax = max(kmax, np.abs(v_ref[a:b]).max())
+    if n == n_el:
+        # the whole mesh: the pattern bit for bit and every value
+        errs["pattern_bit_exact"] = bool(np.array_equal(ro_s, ro) and np.array_equal(cols_s, cols))
+        kd, kmax = np.abs(vals_gpu - v_ref).max(), np.abs(v_ref).max()
+    else:
+        # every row of the nodes whose elements all lie in the sample
+        lens = ro[rows + 1] - ro[rows]
+        assert np.array_equal(lens, ro_s[rows + 1] - ro_s[rows])
+        within = np.arange(lens.sum()) - np.repeat(np.cumsum(lens) - lens, lens)
+        gi = np.repeat(ro[rows], lens) + within
+        si = np.repeat(ro_s[rows], lens) + within
+        errs["pattern_bit_exact"] = bool(np.array_equal(cols[gi], cols_s[si]))
+        kd, kmax = np.abs(vals_gpu[gi] - v_ref[si]).max(), np.abs(v_ref[si]).max()
     errs["f"] = float(ef)
     errs["K"] = float(kd / kmax)
     cpu = cpu_model()
@@ -257,10 +279,12 @@ def bench_mesh(args, torch, wl, wname):
     f_h = f.cpu().numpy()
     v_h = vals.cpu().numpy()
 
-    # the hot path is the pair of kernels k_stage_tile (pass 1) + k_gather
-    # (pass 2), timed together with events on the stream they run on; its
-    # algorithmic bytes are set against the time of the whole call
-    B = mesh_bytes(wl, nnz)
+    # the hot path is the pair of kernels of one call (pass 1 + pass 2), timed
+    # together with events on the stream they run on; the method's algorithmic
+    # bytes are set against the time of the whole call, the library's own count
+    # of what its data layout must move beside them
+    B = method_bytes(wl, nnz)
+    B_layout = mesh_bytes(wl, nnz)
     achieved = B / (ms * 1e-3) / 1e9
     traffic = measured_traffic(wname, args.precision, tuning["gather_shape"])
     kname = {1: "T10", 2: "ANCF3443", 3: "ANCF3243"}[wl.mesh.elem_type]
@@ -290,7 +314,9 @@ def bench_mesh(args, torch, wl, wname):
                      "kernel": (f"k_elem_rows{'' if kname == 'T10' else '_mc'} + k_gather_rows"
                                 f"{'' if kname == 'T10' else '_mc'} ({kname}, f + K)" if rows_path else
                                 f"k_stage_tile + k_gather ({kname}, f + K)"), "kernel_ms": ms,
-                     "pass1_stage_ms": ms1, "pass2_gather_ms": ms2, "algorithmic_bytes": B},
+                     "pass1_stage_ms": ms1, "pass2_gather_ms": ms2, "algorithmic_bytes": B,
+                     "algorithmic_bytes_layout": B_layout,
+                     "frac_layout": B_layout / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         # the same call against the vector arithmetic roofline (contraction FLOPs only)
         "valu": {"flop_per_element": contraction_flop(wl),
                  "achieved_TFLOPs": contraction_flop(wl) * n_el / (ms * 1e-3) / 1e12,
@@ -373,6 +399,7 @@ def bench_mesh(args, torch, wl, wname):
         mesh.set_gather_shape(*[tuning["gather_shape"][k] for k in ("waves", "range_tasks", "range_values")])
         out["fp64"] = {"value": n_el / (ms64 * 1e-3), "ms_per_step": ms64, "tuning": tuning64, "pass1_stage_ms": ms64_1,
                        "pass2_gather_ms": ms64_2, "achieved_GBs": B / (ms64 * 1e-3) / 1e9,
+                       "frac": B / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "valu_frac_fp64": contraction_flop(wl) * n_el / (ms64 * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                        "speedup_mixed_over_fp64": ms64 / ms}
         # mixed against the FP64 GPU result over the whole output
@@ -386,6 +413,20 @@ def bench_mesh(args, torch, wl, wname):
         mesh.vjp(q, qd, w)
         out["vjp_ms"] = time_calls(lambda: mesh.vjp(q, qd, w), max(3, args.steps // 4), torch)
         out["copy_GBs"] = copy_bandwidth(torch)
+    if wname == "t10_beam" and not args.no_batched:
+        # the batched form on the 512 cubes of the batched workload, same precision
+        del f, vals, fn, hn, g
+        torch.cuda.empty_cache()
+        bo = bench_batched(args, torch)
+        out["batched"] = {"workload": bo["config"]["workload"], "bodies": bo["config"]["bodies"],
+                          "elements": bo["config"]["elements"], "nnz": bo["config"]["nnz"],
+                          "graph_ms": bo["ms_per_step"], "loop_ms": bo["per_body_loop"]["ms_per_step"],
+                          "speedup_graph_over_loop": bo["per_body_loop"]["speedup_batched_over_loop"],
+                          "elements_per_s": bo["value"], "achieved_GBs": bo["roofline"]["achieved"],
+                          "frac": bo["roofline"]["frac"], "algorithmic_bytes": bo["roofline"]["algorithmic_bytes"],
+                          "kernel": bo["roofline"]["kernel"], "tuning": bo["tuning"]}
+        print(f"[bench] batched: graph {bo['ms_per_step']:.3f} ms, loop {bo['per_body_loop']['ms_per_step']:.3f} ms",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         base, base_omp, errs, nrows = cpu_baseline(wl, f_h, v_h, ro, cols, h)
         out["cpu_baseline"] = base
@@ -416,7 +457,7 @@ def bench_batched(args, torch):
     f = torch.empty(nd, dtype=torch.float64, device="cuda")
     vals = torch.empty(nz, dtype=torch.float64, device="cuda")
     n_el = sum(wl.mesh.n_elem for wl in wls)
-    B = sum(mesh_bytes(wl, m.nnz) for wl, m in zip(wls, meshes))
+    B = sum(method_bytes(wl, m.nnz) for wl, m in zip(wls, meshes))
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -439,7 +480,8 @@ def bench_batched(args, torch):
         "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_stage_batch + k_gather_batch (one graph)", "kernel_ms": ms,
+                     "kernel": ("k_elem_rows_batch + k_gather_rows_batch (one graph)" if args.precision == "mixed"
+                                else "k_stage_batch + k_gather_batch (one graph)"), "kernel_ms": ms,
                      "algorithmic_bytes": B},
         "per_body_loop": {"ms_per_step": ms_loop, "value": n_el / (ms_loop * 1e-3),
                           "speedup_batched_over_loop": ms_loop / ms},
@@ -459,6 +501,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="t10_beam", choices=list(WORKLOADS) + ["batched"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-cube batched leg of the default run")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--gather-shape", type=int, nargs=3, metavar=("WAVES", "RANGE_TASKS", "RANGE_VALUES"))
     args = ap.parse_args(argv)

@@ -275,13 +275,45 @@ __device__ __forceinline__ unsigned point_update(const MatParams& mp, const doub
   return flags;
 }
 
-// First Piola-Kirchhoff stress per unit value of each material constant, in
-// float64.  P is linear in every constant, P = sum_i theta_i P_i with theta =
-// (lambda, mu) for SVK or (mu10, mu01, kappa) for Mooney-Rivlin, then
-// (eta, lam_v) for Kelvin-Voigt; the parts follow the E-based forms of
-// point_update (parts of an absent law are zero).
-__device__ __forceinline__ void stress_parts(int kind, bool kv, const double* Hd, const double* Fd,
-                                             double (&Pp)[5][9]) {
+// 3x3 helpers (row-major) for the reverse-mode product below
+__device__ __forceinline__ void mm3(const double* A, const double* B, double* C) {  // C = A B
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+__device__ __forceinline__ void mtm3(const double* A, const double* B, double* C) {  // C = A^T B
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = A[i] * B[j] + A[3 + i] * B[3 + j] + A[6 + i] * B[6 + j];
+}
+__device__ __forceinline__ double ddot3(const double* A, const double* B) {
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) s += A[t] * B[t];
+  return s;
+}
+
+// Reverse-mode product of the stress at one point, in float64.  For the
+// cotangent gradient Wc:
+//   Zq_kL = sum_iJ Wc_iJ dP_iJ / dF_kL,   Zd_kL = sum_iJ Wc_iJ dP_iJ / dFdot_kL,
+//   parts[i] = Wc : P_i, P_i the stress per unit value of constant i (P is
+//   linear in every constant: SVK (lambda, mu), MR (mu10, mu01, kappa), then
+//   KV (eta, lam_v), formed even when the law's constant is zero).
+// The adjoints of the E-based forms of point_update, with Y = F^T Wc,
+// Ym = sym(G^T Wc), G = F^-T, sym(A) = (A + A^T) / 2:
+//   SVK : P = F S                 Zq = Wc S + F (lambda tr(Y) I + 2 mu sym(Y))
+//   KV  : P = F S_v               Zq += Wc S_v + Fdot Sh,  Zd = F Sh,
+//                                 Sh = 2 eta sym(Y) + lam_v tr(Y) I
+//   MR  : P = G T(E, J)           Zq = -G T Wc^T G + F (2 mu10 a D1 + 2 mu01 b D2) + c G,
+//     D1 = 2 dev(Ym)   (the adjoint of T's first bracket 2 dev E),
+//     D2 = 2 dev(Ym) + 4 (Ym:E) I + 4 tr(E) Ym - 4 (Ym E + E Ym)
+//          + 8/3 tr(Ym) (E - tr(E) I)   (that of the second bracket B2),
+//     c  = -4/3 mu10 a (Ym : 2 dev E) - 8/3 mu01 b (Ym : B2) + kappa J (2J - 1) tr(Ym)
+//          (the J-dependence of J^-2/3, J^-4/3 and the volumetric term, dJ = J G : dF).
+__device__ __forceinline__ void stress_vjp(const MatParams& mp, const double* Hd, const double* Fd, const double* Wc,
+                                           double* Zq, double* Zd, double* parts) {
   double F[9], E[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) F[t] = Hd[t] + ((t % 4) == 0 ? 1.0 : 0.0);
@@ -291,109 +323,137 @@ __device__ __forceinline__ void stress_parts(int kind, bool kv, const double* Hd
     for (int j = 0; j < 3; ++j)
       E[3 * i + j] = 0.5 * (Hd[3 * i + j] + Hd[3 * j + i] + Hd[i] * Hd[j] + Hd[3 + i] * Hd[3 + j] + Hd[6 + i] * Hd[6 + j]);
   const double trE = E[0] + E[4] + E[8];
-  double T[3][9];  // stress-like factors of the elastic parts: P_i = F T_i (SVK) or G T_i (MR)
+  double Y[9];  // F^T Wc
+  mtm3(F, Wc, Y);
+  const double trY = Y[0] + Y[4] + Y[8];
+  double YE = 0.0;  // sym(Y) : E = Y : E
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const bool d = (t % 4) == 0;
-    T[0][t] = T[1][t] = T[2][t] = 0.0;
-    if (kind == 1) {
-      T[0][t] = d ? trE : 0.0;  // per unit lambda
-      T[1][t] = 2.0 * E[t];     // per unit mu
-    }
-  }
-  double L[9];  // left factor: F (SVK) or G = F^-T (MR)
-#pragma unroll
-  for (int t = 0; t < 9; ++t) L[t] = F[t];
-  if (kind != 1) {
-    const double jm1 = jm1_of(Hd), J = 1.0 + jm1;
-    const double cbJ = cbrt(J), a = 1.0 / (cbJ * cbJ), b = a * a, invJ = 1.0 / J;
-    L[0] = (F[4] * F[8] - F[5] * F[7]) * invJ;
-    L[1] = (F[5] * F[6] - F[3] * F[8]) * invJ;
-    L[2] = (F[3] * F[7] - F[4] * F[6]) * invJ;
-    L[3] = (F[2] * F[7] - F[1] * F[8]) * invJ;
-    L[4] = (F[0] * F[8] - F[2] * F[6]) * invJ;
-    L[5] = (F[1] * F[6] - F[0] * F[7]) * invJ;
-    L[6] = (F[1] * F[5] - F[2] * F[4]) * invJ;
-    L[7] = (F[2] * F[3] - F[0] * F[5]) * invJ;
-    L[8] = (F[0] * F[4] - F[1] * F[3]) * invJ;
-    double EE[9], ee = 0.0;
+  for (int t = 0; t < 9; ++t) YE += Y[t] * E[t];
+  if (mp.kind == 1) {
+    const double lam = mp.c0, mu = mp.c1;
+    parts[0] = trE * trY;
+    parts[1] = 2.0 * YE;
+    parts[2] = 0.0;
+    double S[9], Sh[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        EE[3 * i + j] = E[3 * i] * E[j] + E[3 * i + 1] * E[3 + j] + E[3 * i + 2] * E[6 + j];
-        ee += E[3 * i + j] * E[3 * i + j];
+        const bool d = i == j;
+        S[3 * i + j] = 2.0 * mu * E[3 * i + j] + (d ? lam * trE : 0.0);
+        Sh[3 * i + j] = mu * (Y[3 * i + j] + Y[3 * j + i]) + (d ? lam * trY : 0.0);
       }
+    double A[9], B[9];
+    mm3(Wc, S, A);
+    mm3(F, Sh, B);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) Zq[t] = A[t] + B[t];
+  } else {
+    const double mu10 = mp.c0, mu01 = mp.c1, kap = mp.c2;
+    const double jm1 = jm1_of(Hd), J = 1.0 + jm1;
+    const double cbJ = cbrt(J), a = 1.0 / (cbJ * cbJ), b = a * a, invJ = 1.0 / J;
+    double G[9];
+    G[0] = (F[4] * F[8] - F[5] * F[7]) * invJ;
+    G[1] = (F[5] * F[6] - F[3] * F[8]) * invJ;
+    G[2] = (F[3] * F[7] - F[4] * F[6]) * invJ;
+    G[3] = (F[2] * F[7] - F[1] * F[8]) * invJ;
+    G[4] = (F[0] * F[8] - F[2] * F[6]) * invJ;
+    G[5] = (F[1] * F[6] - F[0] * F[7]) * invJ;
+    G[6] = (F[1] * F[5] - F[2] * F[4]) * invJ;
+    G[7] = (F[2] * F[3] - F[0] * F[5]) * invJ;
+    G[8] = (F[0] * F[4] - F[1] * F[3]) * invJ;
+    double EE[9];
+    mm3(E, E, EE);
+    const double ee = ddot3(E, E);
+    double Ym[9], dev2[9], B2[9];
+    {
+      double T0[9];
+      mtm3(G, Wc, T0);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Ym[3 * i + j] = 0.5 * (T0[3 * i + j] + T0[3 * j + i]);
+    }
+    const double trYm = Ym[0] + Ym[4] + Ym[8];
     const double diag2 = 4.0 / 3.0 * (ee - trE * trE);
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const bool d = (t % 4) == 0;
-      const double dev2 = 2.0 * (E[t] - (d ? trE / 3.0 : 0.0));
-      T[0][t] = 2.0 * a * dev2;
-      T[1][t] = 2.0 * b * (dev2 + 4.0 * trE * E[t] - 4.0 * EE[t] + (d ? diag2 : 0.0));
-      T[2][t] = d ? J * jm1 : 0.0;
+      dev2[t] = 2.0 * (E[t] - (d ? trE / 3.0 : 0.0));
+      B2[t] = dev2[t] + 4.0 * trE * E[t] - 4.0 * EE[t] + (d ? diag2 : 0.0);
     }
+    const double y_dev2 = ddot3(Ym, dev2), y_b2 = ddot3(Ym, B2), ymE = ddot3(Ym, E);
+    parts[0] = 2.0 * a * y_dev2;
+    parts[1] = 2.0 * b * y_b2;
+    parts[2] = J * jm1 * trYm;
+    // -G T Wc^T G
+    double GT[9], M1[9], M2[9];
+    {
+      double T[9];
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+        T[t] = 2.0 * mu10 * a * dev2[t] + 2.0 * mu01 * b * B2[t] + ((t % 4) == 0 ? kap * J * jm1 : 0.0);
+      mm3(G, T, GT);
+    }
+    {
+      double WtG[9];  // Wc^T G
+      mtm3(Wc, G, WtG);
+      mm3(GT, WtG, M1);
+    }
+    double D[9];
+    {
+      double YE2[9], EY[9];
+      mm3(Ym, E, YE2);
+      mm3(E, Ym, EY);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const bool d = (t % 4) == 0;
+        const double dv = 2.0 * (Ym[t] - (d ? trYm / 3.0 : 0.0));
+        const double d2 = dv + (d ? 4.0 * ymE : 0.0) + 4.0 * trE * Ym[t] - 4.0 * (YE2[t] + EY[t]) +
+                          8.0 / 3.0 * trYm * (E[t] - (d ? trE : 0.0));
+        D[t] = 2.0 * mu10 * a * dv + 2.0 * mu01 * b * d2;
+      }
+    }
+    mm3(F, D, M2);
+    const double c = -4.0 / 3.0 * mu10 * a * y_dev2 - 8.0 / 3.0 * mu01 * b * y_b2 + kap * J * (2.0 * J - 1.0) * trYm;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) Zq[t] = M2[t] - M1[t] + c * G[t];
   }
+  // Kelvin-Voigt
+  double Ed[9];
 #pragma unroll
-  for (int p = 0; p < 3; ++p)
+  for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
 #pragma unroll
-      for (int j = 0; j < 3; ++j)
-        Pp[p][3 * i + j] = L[3 * i] * T[p][j] + L[3 * i + 1] * T[p][3 + j] + L[3 * i + 2] * T[p][6 + j];
-  if (kv) {
-    double Ed[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < 3; ++m) s += Fd[3 * m + i] * F[3 * m + j] + F[3 * m + i] * Fd[3 * m + j];
-        Ed[3 * i + j] = 0.5 * s;
-      }
-    const double trEd = Ed[0] + Ed[4] + Ed[8];
+      for (int m = 0; m < 3; ++m) s += Fd[3 * m + i] * F[3 * m + j] + F[3 * m + i] * Fd[3 * m + j];
+      Ed[3 * i + j] = 0.5 * s;
+    }
+  const double trEd = Ed[0] + Ed[4] + Ed[8];
+  parts[3] = 2.0 * ddot3(Y, Ed);
+  parts[4] = trEd * trY;
+  const double eta = mp.eta, lv = mp.lam_v;
+  if (eta != 0.0 || lv != 0.0) {
+    double Sv[9], Sh[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        Pp[3][3 * i + j] = 2.0 * (F[3 * i] * Ed[j] + F[3 * i + 1] * Ed[3 + j] + F[3 * i + 2] * Ed[6 + j]);
-        Pp[4][3 * i + j] = F[3 * i + j] * trEd;
+        const bool d = i == j;
+        Sv[3 * i + j] = 2.0 * eta * Ed[3 * i + j] + (d ? lv * trEd : 0.0);
+        Sh[3 * i + j] = eta * (Y[3 * i + j] + Y[3 * j + i]) + (d ? lv * trY : 0.0);
       }
+    double A[9], B[9];
+    mm3(Wc, Sv, A);
+    mm3(Fd, Sh, B);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) Zq[t] += A[t] + B[t];
+    mm3(F, Sh, Zd);
   } else {
 #pragma unroll
-    for (int t = 0; t < 9; ++t) Pp[3][t] = Pp[4][t] = 0.0;
+    for (int t = 0; t < 9; ++t) Zd[t] = 0.0;
   }
-}
-
-// Z_kL = sum_iJ Wc_iJ dP_v,iJ / dFdot_kL: the viscous tangent of the rate
-// applied to a cotangent gradient, from
-//   dP_v,iJ / dFdot_kL = eta (F_iL F_kJ + (F F^T)_ik d_JL) + lam_v F_iJ F_kL
-// giving Z = eta (F Wc^T F + F F^T Wc) + lam_v (Wc : F) F.
-__device__ __forceinline__ void rate_cotangent(double eta, double lam_v, const double* Hd, const double* Wc,
-                                               double* Z) {
-  double F[9];
-#pragma unroll
-  for (int t = 0; t < 9; ++t) F[t] = Hd[t] + ((t % 4) == 0 ? 1.0 : 0.0);
-  double WtF[9], FtW[9], wf = 0.0;  // Wc^T F and F^T Wc
-#pragma unroll
-  for (int J = 0; J < 3; ++J)
-#pragma unroll
-    for (int L = 0; L < 3; ++L) {
-      WtF[3 * J + L] = Wc[J] * F[L] + Wc[3 + J] * F[3 + L] + Wc[6 + J] * F[6 + L];
-      FtW[3 * J + L] = F[J] * Wc[L] + F[3 + J] * Wc[3 + L] + F[6 + J] * Wc[6 + L];
-    }
-#pragma unroll
-  for (int t = 0; t < 9; ++t) wf += Wc[t] * F[t];
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-#pragma unroll
-    for (int L = 0; L < 3; ++L) {
-      double z = lam_v * wf * F[3 * k + L];
-#pragma unroll
-      for (int J = 0; J < 3; ++J) z += eta * (F[3 * k + J] * WtF[3 * J + L] + F[3 * k + J] * FtW[3 * J + L]);
-      Z[3 * k + L] = z;
-    }
 }
 
 // Z_kL = sum_iJ Wc_iJ A_iJkL (the tangent applied to a cotangent gradient Wc

@@ -3,8 +3,7 @@
 // For a cotangent w the library returns, without forming K:
 //   gq     = (df/dq)^T w     : per point Z_kL = sum_iJ W_iJ dP_iJ/dF_kL with
 //                              W = sum_a w_a (x) g_a, then gq_b = sum dV Z g_b
-//   gqdot  = (df/dqdot)^T w  : the same with dP/dFdot (the Kelvin-Voigt rate
-//                              tangent, in closed form)
+//   gqdot  = (df/dqdot)^T w  : the same with dP/dFdot
 //   gparam = d(w . f)/dtheta : P is linear in every material constant, so the
 //                              partial is sum dV W : P_i with P_i the stress per
 //                              unit constant; SVK (E, nu) follow by the chain
@@ -15,7 +14,8 @@
 //
 // Shaped like the force-only path: one workgroup holds whole elements, their
 // nodal values (u, qdot, w) go to LDS once, a lane per point runs one
-// constitutive update for both products and the parameter parts, the points'
+// reverse-mode stress product (stress_vjp) for both products and the
+// parameter parts, the points'
 // Zhat = dV Z J0^-T stay in LDS, and a lane per (element, coefficient) sums them
 // against the parent gradients into one block per incidence.  The per-node
 // sums then run in a fixed order (the force path's pass 2), and the parameter
@@ -91,33 +91,15 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_elem(AsmArgs a, const doubl
   }
   __syncthreads();  // the nodal values are consumed: the LDS holds Zhat from here on
   const double dV = det * Rule::w_rt(q);
-  const bool kv = a.mp.eta != 0.0 || a.mp.lam_v != 0.0;
-  double Zq[9], Zd[9];
-  {
-    PointOut<double> o;
-    (void)point_update<double, true>(a.mp, Hd, Fd, dV, 1.0, 0.0, o);
-    cotangent_contract(o, Wg, Zq);
+  double Zq[9], Zd[9], part[5];
+  stress_vjp(a.mp, Hd, Fd, Wg, Zq, Zd, part);
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    Zq[t] *= dV;
+    Zd[t] *= dV;
   }
-  if (bqd && kv) {
-    rate_cotangent(a.mp.eta, a.mp.lam_v, Hd, Wg, Zd);
 #pragma unroll
-    for (int t = 0; t < 9; ++t) Zd[t] *= dV;
-  } else {
-#pragma unroll
-    for (int t = 0; t < 9; ++t) Zd[t] = 0.0;
-  }
-  double part[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (gpart && act) {
-    double Pp[5][9];  // the viscous parts too when the damping is off: d(w . f)/d eta is not zero there
-    stress_parts(a.mp.kind, true, Hd, Fd, Pp);
-#pragma unroll
-    for (int th = 0; th < 5; ++th) {
-      double c = 0.0;
-#pragma unroll
-      for (int t = 0; t < 9; ++t) c += Wg[t] * Pp[th][t];
-      part[th] = dV * c;
-    }
-  }
+  for (int th = 0; th < 5; ++th) part[th] = act ? dV * part[th] : 0.0;
   double* zr = reinterpret_cast<double*>(smem);  // Zhat of q at 18 p, of qdot at 18 p + 9
   if (act) {
 #pragma unroll

@@ -44,3 +44,15 @@ def test_algorithmic_bytes_formula():
     assert bench.mesh_bytes(wb, nnz_b) == (8 * nnz_b + 32 * n_dof_b + 4 * (n_dof_b + 1)
                                            + 5 * (4 * 2 + 80 + 16 + 4))
     assert np.all(np.diff(ro) >= 0)
+
+
+def test_method_bytes_formula():
+    """The roofline's byte count: 8 nnz + 24 n_dof + n_el (4 m + G + 4 n_en^2);
+    at the 200 x 20 x 20 beam's sizes (169,094,889 values, 2,022,243 DOF,
+    480,000 elements) it is 1,650.9 MB."""
+    wl = W.config1()
+    ro, cols = oracle.csr_pattern(oracle.Mesh.of(wl.mesh))
+    nnz, n_dof, n_el = len(cols), wl.mesh.n_dof, wl.mesh.n_elem
+    assert bench.method_bytes(wl, nnz) == 8 * nnz + 24 * n_dof + n_el * (40 + 80 + 400)
+    b5 = 8 * 169_094_889 + 24 * 2_022_243 + 480_000 * (40 + 80 + 400)
+    assert round(b5 / 1e5) == 16509

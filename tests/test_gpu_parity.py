@@ -145,45 +145,52 @@ def test_config2_full_size():
     m.close()
 
 
+_CONFIG5 = {}
+
+
+def _config5_reference():
+    """The 480,000-element beam, its oracle CSR pattern and its oracle f and K
+    (h = 1e-3), computed once for both precisions."""
+    if not _CONFIG5:
+        wl = W.config5()
+        om = oracle.Mesh.of(wl.mesh)
+        pat = oracle.csr_pattern(om)
+        f_ref, v_ref = oracle.assemble(om, oracle.material_of(wl.material), wl.q, wl.qdot, 1e-3, 1.0, pattern=pat)
+        _CONFIG5.update(wl=wl, pat=pat, f=f_ref, v=v_ref)
+    return _CONFIG5
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_config5_sampled(precision):
-    """480,000 T10 elements at full size in the benchmark's launch: rows of
-    sampled nodes against the oracle (all their contributions), plus the
-    momentum invariant over the whole force vector."""
-    print(f"[gpu] config5 sampled {precision}", flush=True)
-    wl = W.config5()
+def test_config5_full(precision):
+    """480,000 T10 elements at full size in the benchmark's launch: the CSR
+    pattern bit-exact against the oracle's (row offsets and all 169,094,889
+    columns), every value of f and K against the oracle, and the momentum
+    invariant over the whole force vector (also for the force-only path)."""
+    print(f"[gpu] config5 full {precision}", flush=True)
+    ref = _config5_reference()
+    wl = ref["wl"]
     m = make_mesh(wl, precision)
-    q, qd = cuda(wl.q), cuda(wl.qdot)
-    h = 1e-3
-    f, vals = m.assemble(q, qd, h, 1.0)
     ro, cols = m.csr_pattern(on_device=False)
-    fh, vh = f.cpu().numpy(), vals.cpu().numpy()
-    rng = np.random.default_rng(55)
-    n_nodes = wl.mesh.n_coef
-    nodes = np.concatenate([[0, n_nodes - 1, n_nodes // 2], rng.choice(n_nodes, 40, replace=False)])
-    om = oracle.Mesh.of(wl.mesh)
-    omat = oracle.material_of(wl.material)
-    f_ref, rows_ref, rows = oracle_rows(om, omat, wl, h, 1.0, nodes)
-    got = dense_rows(ro.numpy(), cols.numpy(), vh, rows)
-    fmax = np.abs(f_ref[rows]).max()
-    kmax = max(max(abs(v) for v in r.values()) for r in rows_ref.values())
-    ef = np.abs(fh[rows] - f_ref[rows]).max() / fmax
-    ek = 0.0
-    for r in rows:
-        assert set(got[r].keys()) == set(rows_ref[r].keys())  # CSR row = adjacency of the node
-        for c, v in rows_ref[r].items():
-            ek = max(ek, abs(got[r][c] - v) / kmax)
-    print(f"  config5 {precision}: sampled f {ef:.2e}  K {ek:.2e}", flush=True)
+    assert np.array_equal(ro.numpy(), ref["pat"][0])
+    assert np.array_equal(cols.numpy(), ref["pat"][1])
+    del ro, cols
+    q, qd = cuda(wl.q), cuda(wl.qdot)
+    f, vals = m.assemble(q, qd, 1e-3, 1.0)
+    fh = f.cpu().numpy()
+    ef, ef2 = rel_err(fh, ref["f"])
+    ek, ek2 = rel_err(vals.cpu().numpy(), ref["v"])
+    del vals
+    print(f"  config5 {precision}: f {ef:.2e} ({ef2:.2e})  K {ek:.2e} ({ek2:.2e})", flush=True)
     assert ef <= TOL[precision] and ek <= TOL[precision]
     # momentum: each element's forces sum to zero up to the rounding of its own
     # arithmetic (float32 in the mixed path), a random walk over the elements
     fv = fh.reshape(-1, 3)
     eps = 1e-9 if precision == "fp64" else 1e-6
     assert np.abs(fv.sum(axis=0)).max() <= eps * np.abs(fv).max() * np.sqrt(len(fv))
-    # the force-only path on the same mesh: sampled rows and the same invariant
+    # the force-only path on the same mesh
     fo = m.internal_force(q, qd).cpu().numpy()
-    ef0 = np.abs(fo[rows] - f_ref[rows]).max() / fmax
-    print(f"  config5 {precision}: force-only sampled f {ef0:.2e}", flush=True)
+    ef0 = rel_err(fo, ref["f"])[0]
+    print(f"  config5 {precision}: force-only f {ef0:.2e}", flush=True)
     assert ef0 <= TOL[precision]
     fov = fo.reshape(-1, 3)
     assert np.abs(fov.sum(axis=0)).max() <= eps * np.abs(fov).max() * np.sqrt(len(fov))
@@ -194,11 +201,16 @@ def test_config5_sampled(precision):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_config3_sampled(precision):
     """The 256 x 256 ANCF3443 plate (65,536 elements, 3x3x2 rule) at full size in
-    the benchmark's launch: rows of sampled nodes (all 12 coefficient rows)
-    against the oracle."""
+    the benchmark's launch: the CSR pattern bit-exact against the oracle's
+    (85,155,984 columns), and the rows of 517 sampled nodes (all 12 coefficient
+    rows, every contribution) against the oracle."""
     print(f"[gpu] config3 sampled {precision}", flush=True)
     wl = W.config3()
     m = make_mesh(wl, precision)
+    ro_ref, cols_ref = oracle.csr_pattern(oracle.Mesh.of(wl.mesh))
+    ro_g, cols_g = m.csr_pattern(on_device=False)
+    assert np.array_equal(ro_g.numpy(), ro_ref) and np.array_equal(cols_g.numpy(), cols_ref)
+    del ro_g, cols_g, ro_ref, cols_ref
     h = 1e-3
     f, vals = m.assemble(cuda(wl.q), cuda(wl.qdot), h, 1.0)
     ro, cols = m.csr_pattern(on_device=False)
@@ -206,7 +218,7 @@ def test_config3_sampled(precision):
     n_nodes = int(wl.mesh.conn.max()) + 1
     rng = np.random.default_rng(33)
     # corners, an edge node, the centre and random interior nodes
-    nodes = np.concatenate([[0, 256, n_nodes - 1, 128, n_nodes // 2], rng.choice(n_nodes, 12, replace=False)])
+    nodes = np.concatenate([[0, 256, n_nodes - 1, 128, n_nodes // 2], rng.choice(n_nodes, 512, replace=False)])
     om = oracle.Mesh.of(wl.mesh)
     f_ref, rows_ref, rows = oracle_rows(om, oracle.material_of(wl.material), wl, h, 1.0, nodes)
     got = dense_rows(ro.numpy(), cols.numpy(), vh, rows)

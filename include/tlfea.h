@@ -346,6 +346,22 @@ int tlfea_adamw_solve(tlfea_mesh_t mesh, const tlfea_adamw_params* params, doubl
                       int32_t max_iters, int32_t check_every, double eps_in, double eps_rel,
                       int32_t* iters_out, double* gnorm_out, void* stream);
 
+/* The internal force and its VJP with the material constants read from device
+ * memory instead of the mesh (Sec. 4.3, Stage 1; the VJP as for
+ * tlfea_internal_force_vjp): d_params = (p0, p1, p2, kv_eta, kv_lambda), 5
+ * float64 on the device, with p as in tlfea_mesh_desc for the mesh's material
+ * kind (SVK: E, nu, unused; Mooney-Rivlin: mu10, mu01, kappa).  The mesh's own
+ * constants are neither used nor changed, and no call synchronises with the
+ * host: for differentiable callers whose constants live on the GPU (the torch
+ * autograd wrapper).  Needs the pattern.  tlfea_internal_force_p takes the
+ * force path of tlfea_internal_force (the same kernels and summation order);
+ * d_gparam of the VJP holds d(w . f)/d(p0, p1, p2, kv_eta, kv_lambda) at
+ * d_params. */
+int tlfea_internal_force_p(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, const double* d_params,
+                           double* d_f, void* stream);
+int tlfea_internal_force_vjp_p(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, const double* d_params,
+                               const double* d_w, double* d_gq, double* d_gqdot, double* d_gparam, void* stream);
+
 /* Read (and synchronise on the mesh's last stream) the runtime flag bits,
  * then clear them. */
 int tlfea_get_runtime_flags(tlfea_mesh_t mesh, uint32_t* flags);
@@ -393,7 +409,12 @@ int tlfea_mesh_autotune(tlfea_mesh_t mesh, const double* d_q, const double* d_qd
  * q/qdot/f[dof_off[b] .. dof_off[b+1]) and vals[nnz_off[b] .. nnz_off[b+1]).
  * All meshes must be of the same element type and have built patterns; they
  * must stay alive while the batch exists.  Materials and precision are read
- * from the meshes at tlfea_batch_create (mixed SVK / Mooney-Rivlin allowed).
+ * from the meshes at tlfea_batch_create (mixed SVK / Mooney-Rivlin allowed),
+ * together with the device arrays of their patterns: after
+ * tlfea_build_csr_pattern, tlfea_mesh_set_material or tlfea_mesh_set_precision
+ * (to another precision) on a member, every call on the batch (the graph and
+ * loop forms alike) returns TLFEA_ERR_INVALID and writes nothing; create the
+ * batch again.
  * ------------------------------------------------------------------------- */
 int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, tlfea_batch_t* out);
 int tlfea_batch_destroy(tlfea_batch_t batch);

@@ -26,7 +26,7 @@ EXPORTED = [
     "tlfea_status_string", "tlfea_version", "tlfea_mesh_create", "tlfea_mesh_destroy", "tlfea_mesh_info",
     "tlfea_mesh_set_material", "tlfea_mesh_set_precision", "tlfea_build_csr_pattern", "tlfea_get_csr_pattern",
     "tlfea_get_slot_map", "tlfea_internal_force", "tlfea_internal_force_noalloc", "tlfea_tangent", "tlfea_tangent_ex", "tlfea_assemble",
-    "tlfea_assemble_ex", "tlfea_assemble_accumulate", "tlfea_assemble_points", "tlfea_assemble_nodes", "tlfea_internal_force_vjp", "tlfea_get_runtime_flags", "tlfea_batch_create",
+    "tlfea_assemble_ex", "tlfea_assemble_accumulate", "tlfea_assemble_points", "tlfea_assemble_nodes", "tlfea_internal_force_vjp", "tlfea_internal_force_p", "tlfea_internal_force_vjp_p", "tlfea_get_runtime_flags", "tlfea_batch_create",
     "tlfea_batch_destroy", "tlfea_batch_offsets", "tlfea_batch_assemble", "tlfea_batch_assemble_loop",
     "tlfea_mesh_set_gather_shape", "tlfea_mesh_get_gather_shape", "tlfea_mesh_autotune",
     "tlfea_batch_set_gather_shape", "tlfea_batch_get_gather_shape", "tlfea_batch_autotune",
@@ -106,6 +106,8 @@ def lib() -> ctypes.CDLL:
         "tlfea_assemble_points": ([vp, vp, vp, dbl, dbl, i32, vp], ctypes.c_int),
         "tlfea_assemble_nodes": ([vp, vp, vp, i32, vp], ctypes.c_int),
         "tlfea_internal_force_vjp": ([vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "tlfea_internal_force_p": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "tlfea_internal_force_vjp_p": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "tlfea_get_runtime_flags": ([vp, P(ctypes.c_uint32)], ctypes.c_int),
         "tlfea_batch_create": ([P(vp), i32, P(vp)], ctypes.c_int),
         "tlfea_batch_destroy": ([vp], ctypes.c_int),

@@ -195,6 +195,28 @@ class TLMesh:
                 "tlfea_internal_force_vjp")
         return gq, gqd, gp
 
+    def internal_force_p(self, q, qdot, params, out=None):
+        """f_int with the material constants taken from the device vector
+        ``params`` = (p0, p1, p2, kv_eta, kv_lambda) (float64, 5, same GPU); the
+        mesh's own constants are neither used nor changed, nothing synchronises."""
+        out = torch.empty(self.n_dof, dtype=torch.float64, device=q.device) if out is None else out
+        N.check(N.lib().tlfea_internal_force_p(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof),
+                                               _ptr(params, n=5), _ptr(out, n=self.n_dof), _stream()),
+                "tlfea_internal_force_p")
+        return out
+
+    def vjp_p(self, q, qdot, params, w, want_q=True, want_qdot=True, want_params=True):
+        """vjp() at the device material vector ``params`` (see internal_force_p)."""
+        dev = q.device
+        gq = torch.empty(self.n_dof, dtype=torch.float64, device=dev) if want_q else None
+        gqd = torch.empty(self.n_dof, dtype=torch.float64, device=dev) if want_qdot else None
+        gp = torch.empty(5, dtype=torch.float64, device=dev) if want_params else None
+        N.check(N.lib().tlfea_internal_force_vjp_p(self._h, _ptr(q, n=self.n_dof), _ptr(qdot, n=self.n_dof),
+                                                   _ptr(params, n=5), _ptr(w, n=self.n_dof), _ptr(gq), _ptr(gqd),
+                                                   _ptr(gp), _stream()),
+                "tlfea_internal_force_vjp_p")
+        return gq, gqd, gp
+
     def build_upper_pattern(self) -> int:
         """Build the upper-triangle pattern (rows cut at the diagonal); returns nnz_upper."""
         n = ctypes.c_int64()

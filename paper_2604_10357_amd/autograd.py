@@ -14,27 +14,30 @@ from .workloads import Material
 
 
 class InternalForce(torch.autograd.Function):
+    """Forward and backward read the material vector on the device
+    (tlfea_internal_force_p / tlfea_internal_force_vjp_p): no host
+    synchronisation, and the mesh's own material is left as it was."""
+
     @staticmethod
     def forward(ctx, mesh: TLMesh, q, qdot, params):
-        vals = params.detach().double().cpu().tolist()
-        mat = Material(mesh.material.kind, tuple(vals[:3]), vals[3], vals[4])
-        mesh.set_material(mat)
-        f = mesh.internal_force(q.detach(), None if qdot is None else qdot.detach())
+        p = params.detach().to(device=q.device, dtype=torch.float64).contiguous()
+        f = mesh.internal_force_p(q.detach(), None if qdot is None else qdot.detach(), p)
         ctx.mesh = mesh
-        ctx.mat = mat
-        ctx.save_for_backward(q, qdot if qdot is not None else torch.zeros_like(q))
         ctx.has_qdot = qdot is not None
+        ctx.save_for_backward(q, qdot if qdot is not None else torch.zeros_like(q), p)
         return f
 
     @staticmethod
     def backward(ctx, grad_f):
-        q, qdot = ctx.saved_tensors
+        q, qdot, p = ctx.saved_tensors
         mesh: TLMesh = ctx.mesh
-        mesh.set_material(ctx.mat)
         want_q, want_qd, want_p = ctx.needs_input_grad[1], ctx.needs_input_grad[2], ctx.needs_input_grad[3]
-        gq, gqd, gp = mesh.vjp(q.detach(), qdot.detach(), grad_f.contiguous().double(),
-                               want_q=want_q or True, want_qdot=want_qd and ctx.has_qdot, want_params=want_p)
-        return None, (gq if want_q else None), (gqd if want_qd and ctx.has_qdot else None), gp
+        want_qd = want_qd and ctx.has_qdot
+        if not (want_q or want_qd or want_p):
+            return None, None, None, None
+        gq, gqd, gp = mesh.vjp_p(q.detach(), qdot.detach(), p, grad_f.contiguous().double(),
+                                 want_q=want_q, want_qdot=want_qd, want_params=want_p)
+        return None, gq, gqd, gp
 
 
 def material_vector(material: Material, device) -> torch.Tensor:

@@ -1,16 +1,21 @@
-// adamw.hip -- the first-order inner solver of a time step (Sec. 4.5, Alg. 2,
-// without constraint terms): AdamW on g(v) = M (v - v_n)/h + f_int(q_n + h v, v)
-// - f_ext, the gradient of the incremental potential in the velocity.
+// adamw.hip -- the first-order inner solver of a time step (Sec. 4.5, without
+// constraint terms): the velocity v minimises the incremental potential whose
+// gradient is g(v) = M (v - v_n)/h + f_int(q_n + h v, v) - f_ext, by AdamW, the
+// Adam method with decoupled weight decay (Loshchilov and Hutter, ICLR 2019):
+//   m <- b1 m + (1 - b1) g,   s <- b2 s + (1 - b2) g^2            (moments)
+//   v <- v - lr (m / (1 - b1^l) / (sqrt(s / (1 - b2^l)) + eps) + wd v)
+// at iteration l, then q = q_n + h v for the next force evaluation.
 //
-// Each inner iteration is four launches on the caller's stream: the iteration
-// counter (one lane), the per-DOF AdamW update fused with the step map
-// q = q_n + h v, the internal force (both passes of the assembly, force only),
-// and the gradient over the mass rows.  The iterations between two convergence
-// checks are captured once into a HIP graph and replayed; the bias corrections
-// read the counter from device memory, so the captured arguments never change.
-// Convergence (||g|| <= eps_in (1 + ||v||) or ||g|| <= eps_rel ||g_0||, g_0 the
-// first gradient) is checked on the host from norms reduced on the device in a
-// fixed order.
+// Arranged for the GPU: each inner iteration is four launches on the caller's
+// stream.  A one-lane kernel advances the iteration counter and forms the two
+// bias-correction factors in device memory (so no per-DOF power is taken and
+// the captured arguments never change); one per-DOF kernel applies the moment
+// and velocity updates fused with q = q_n + h v; then the internal force (both
+// passes of the force-only assembly) and the gradient over the mass rows.  The
+// iterations between two convergence checks are captured once into a HIP graph
+// and replayed.  Convergence (||g|| <= eps_in (1 + ||v||) or ||g|| <= eps_rel
+// ||g_0||, g_0 the first gradient) is checked on the host from norms reduced on
+// the device in a fixed order.
 #include <cmath>
 
 #include "tlfea_internal.h"
@@ -31,27 +36,30 @@ __global__ void k_fill(double* p, int64_t n) {
     p[i] = 0.0;
 }
 
-__global__ void k_count(int64_t* l) {
-  if (threadIdx.x == 0) *l += 1;
+// the iteration counter l and the bias-correction divisors 1 - b1^l, 1 - b2^l
+__global__ void k_count(AdamwArgs p, int64_t* l, double* corr) {
+  if (threadIdx.x != 0) return;
+  const int64_t it = *l + 1;
+  *l = it;
+  corr[0] = 1.0 - std::pow(p.beta1, (double)it);
+  corr[1] = 1.0 - std::pow(p.beta2, (double)it);
 }
 
-// m, s moments; v and q = q_n + h v updated in place (Alg. 2, the five
-// per-DOF steps of an inner iteration)
-__global__ void k_adamw(AdamwArgs p, const int64_t* l, int64_t n, const double* g, const double* q_n, double* m,
-                        double* s, double* v, double* q) {
+// per DOF: the two moments, the decoupled-decay velocity update and the step map
+__global__ void k_adamw(AdamwArgs p, const double* __restrict__ corr, int64_t n, const double* __restrict__ g,
+                        const double* __restrict__ q_n, double* __restrict__ m, double* __restrict__ s,
+                        double* __restrict__ v, double* __restrict__ q) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double it = (double)*l;
   const double gi = g[i];
   const double mi = p.beta1 * m[i] + (1.0 - p.beta1) * gi;
   const double si = p.beta2 * s[i] + (1.0 - p.beta2) * gi * gi;
   m[i] = mi;
   s[i] = si;
-  const double mh = mi / (1.0 - std::pow(p.beta1, it));
-  const double sh = si / (1.0 - std::pow(p.beta2, it));
-  const double vi = (1.0 - p.lr * p.wd) * v[i] - p.lr * mh / (std::sqrt(sh) + p.eps);
-  v[i] = vi;
-  q[i] = q_n[i] + p.h * vi;
+  const double vi = v[i];
+  const double vn = vi - p.lr * ((mi / corr[0]) / (std::sqrt(si / corr[1]) + p.eps) + p.wd * vi);
+  v[i] = vn;
+  q[i] = q_n[i] + p.h * vn;
 }
 
 // partial sums of g.g and v.v per block (fixed order), then one block adds them
@@ -102,8 +110,10 @@ int adamw_iteration(tlfea_mesh_t mesh, const tlfea::AdamwArgs& a, const double* 
                     int64_t* d_l, hipStream_t s) {
   const Mesh& me = mesh->m;
   const int64_t n = me.n_dof;
-  hipLaunchKernelGGL(tlfea::k_count, dim3(1), dim3(64), 0, s, d_l);
-  hipLaunchKernelGGL(tlfea::k_adamw, dim3(tlfea::blocks_for(n)), dim3(256), 0, s, a, d_l, n, g, q_n, m, sm, v, q);
+  double* corr = reinterpret_cast<double*>(d_l + 1);  // the two divisors follow the counter
+  hipLaunchKernelGGL(tlfea::k_count, dim3(1), dim3(64), 0, s, a, d_l, corr);
+  hipLaunchKernelGGL(tlfea::k_adamw, dim3(tlfea::blocks_for(n)), dim3(256), 0, s, a, corr, n, g, q_n, m, sm, v,
+                     q);
   TLFEA_HIP_CHECK(hipGetLastError());
   int rc = tlfea_internal_force(mesh, q, v, f, s);
   if (rc) return rc;
@@ -132,16 +142,16 @@ TLFEA_API int tlfea_adamw_solve(tlfea_mesh_t mesh, const tlfea_adamw_params* p, 
   double* sec = d_work + n;
   double* g = d_work + 2 * n;
   double* f = d_work + 3 * n;
-  // device scalars: iteration counter, norm partials and norms
+  // device scalars: iteration counter, bias-correction divisors, norm partials and norms
   if (!m.d_solver) {
-    if (hipMalloc(&m.d_solver, sizeof(double) * (2 * tlfea::kNormBlocks + 4)) != hipSuccess) {
+    if (hipMalloc(&m.d_solver, sizeof(double) * (2 * tlfea::kNormBlocks + 6)) != hipSuccess) {
       (void)hipGetLastError();
       return TLFEA_ERR_NOMEM;
     }
   }
   auto* d_l = reinterpret_cast<int64_t*>(m.d_solver);
-  double* part = m.d_solver + 2;
-  double* norms = m.d_solver + 2 + 2 * tlfea::kNormBlocks;
+  double* part = m.d_solver + 3;
+  double* norms = m.d_solver + 3 + 2 * tlfea::kNormBlocks;
   const tlfea::AdamwArgs a{p->lr, p->beta1, p->beta2, p->eps, p->weight_decay, h};
   // g = m = s = 0 and l = 0 (fill kernels: nothing here is a memset)
   hipLaunchKernelGGL(tlfea::k_fill, dim3(tlfea::blocks_for(3 * n)), dim3(256), 0, s, d_work, 3 * n);

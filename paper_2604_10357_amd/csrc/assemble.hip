@@ -1127,7 +1127,8 @@ __global__ __launch_bounds__(kForceThreads) void k_elem_force(AsmArgs a, const i
   tile_kinematics<Rule, (NEN > 8)>(a, nod + 6 * NEN * el, e0 + el, q, Jinv, det, Hd, Fd);
   __syncthreads();  // the nodal values are consumed: the LDS holds Phat from here on
   PointOut<R> o;
-  const unsigned fl = point_update<R, false>(a.mp, Hd, Fd, det * Rule::w_rt(q), a.alpha, a.beta, o);
+  const MatParams mp = launch_material(a);
+  const unsigned fl = point_update<R, false>(mp, Hd, Fd, det * Rule::w_rt(q), a.alpha, a.beta, o);
   if (act && fl) atomicOr(a.flags, fl);
   HatOut<R> h;
   to_parent<R, false>(o, Jinv, h);
@@ -1539,6 +1540,40 @@ int launch_force_noalloc(const Mesh& m, const AsmArgs& a, double* f, hipStream_t
   int rc = m.precision == TLFEA_MIXED ? launch_force_prec<float>(m, a, blk, s) : launch_force_prec<double>(m, a, blk, s);
   if (rc) return rc;
   return launch_force_sum(m, blk, f, false, s);
+}
+
+int launch_force_blocks(Mesh& m, const AsmArgs& a, double* f, hipStream_t s) {
+  if (!m.d_incpos) return TLFEA_ERR_NO_PATTERN;
+  const size_t rsz = m.precision == TLFEA_MIXED ? sizeof(float) : sizeof(double);
+  if (int rc = ensure_stage(m, (size_t)m.n_elem * m.n_pn * 3 * m.mc * rsz)) return rc;
+  int rc = m.precision == TLFEA_MIXED ? launch_force_prec<float>(m, a, m.d_stage, s)
+                                      : launch_force_prec<double>(m, a, m.d_stage, s);
+  m.staged = rc ? 0 : 4;
+  m.staged_precision = m.precision;
+  if (rc) return rc;
+  return launch_force_sum(m, m.d_stage, f, false, s);
+}
+
+__global__ void k_params(int kind, const double* __restrict__ p, double* __restrict__ mp) {
+  if (threadIdx.x != 0) return;
+  if (kind == TLFEA_SVK) {
+    const double E = p[0], nu = p[1];
+    mp[0] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    mp[1] = E / (2.0 * (1.0 + nu));
+    mp[2] = 0.0;
+  } else {
+    mp[0] = p[0];
+    mp[1] = p[1];
+    mp[2] = p[2];
+  }
+  mp[3] = p[3];
+  mp[4] = p[4];
+}
+
+int launch_params(const Mesh& m, const double* d_params, hipStream_t s) {
+  hipLaunchKernelGGL(k_params, dim3(1), dim3(64), 0, s, m.material, d_params, m.d_mp);
+  TLFEA_HIP_CHECK(hipGetLastError());
+  return TLFEA_OK;
 }
 
 int launch_block_sum(const Mesh& m, const double* blk, double* out, hipStream_t s) {

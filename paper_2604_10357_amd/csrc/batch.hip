@@ -20,6 +20,7 @@ using tlfea::BatchRange;
 
 struct tlfea_batch_s {
   std::vector<tlfea_mesh_t> meshes;
+  std::vector<uint64_t> generation;  // each member's generation when the batch copied its state
   int device = 0;
   int elem_type = 0, gl0 = 0, precision = TLFEA_FP64;
   std::vector<int64_t> dof_off, nnz_off;
@@ -164,6 +165,7 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
       return TLFEA_ERR_TOO_LARGE;
     }
     b->meshes.push_back(meshes[i]);
+    b->generation.push_back(m.generation);
   }
   if (b->n_blocks > INT32_MAX || b->n_rblocks > INT32_MAX) { delete b; return TLFEA_ERR_TOO_LARGE; }
   const size_t stage = b->rows ? (size_t)b->n_inc * tlfea::row_block_bytes()
@@ -204,6 +206,14 @@ TLFEA_API int tlfea_batch_offsets(tlfea_batch_t batch, int64_t* dof_off, int64_t
   return TLFEA_OK;
 }
 
+// The batch holds copies of its members' device pointers, materials and
+// precision: any later change to a member makes it stale.
+static bool batch_current(tlfea_batch_t b) {
+  for (size_t i = 0; i < b->meshes.size(); ++i)
+    if (b->meshes[i]->m.generation != b->generation[i]) return false;
+  return true;
+}
+
 static BatchArgs batch_args(tlfea_batch_t b, const double* d_q, const double* d_qdot, const double* d_h,
                             double* d_f, double* d_vals) {
   BatchArgs a{};
@@ -232,6 +242,7 @@ static int batch_enqueue(tlfea_batch_t b, const BatchArgs& a, hipStream_t s) {
 TLFEA_API int tlfea_batch_assemble(tlfea_batch_t b, const double* d_q, const double* d_qdot, const double* d_h,
                                    double* d_f, double* d_vals, void* stream) {
   if (!b || !d_q || !d_h || !d_f || !d_vals) return TLFEA_ERR_INVALID;
+  if (!batch_current(b)) return TLFEA_ERR_INVALID;
   if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
   const BatchArgs a = batch_args(b, d_q, d_qdot, d_h, d_f, d_vals);
   auto s = (hipStream_t)stream;
@@ -267,6 +278,7 @@ TLFEA_API int tlfea_batch_assemble(tlfea_batch_t b, const double* d_q, const dou
 TLFEA_API int tlfea_batch_assemble_loop(tlfea_batch_t b, const double* d_q, const double* d_qdot,
                                         const double* d_h, double* d_f, double* d_vals, void* stream) {
   if (!b || !d_q || !d_h || !d_f || !d_vals) return TLFEA_ERR_INVALID;
+  if (!batch_current(b)) return TLFEA_ERR_INVALID;
   if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
   const size_t n = b->meshes.size();
   std::vector<double> h(n);
@@ -283,6 +295,7 @@ TLFEA_API int tlfea_batch_assemble_loop(tlfea_batch_t b, const double* d_q, cons
 
 TLFEA_API int tlfea_batch_set_gather_shape(tlfea_batch_t b, const tlfea_gather_shape* shape) {
   if (!b || !shape) return TLFEA_ERR_INVALID;
+  if (!batch_current(b)) return TLFEA_ERR_INVALID;
   return batch_set_shape(b, tlfea::GatherTuning{shape->waves, shape->range_tasks, shape->range_values});
 }
 
@@ -301,6 +314,7 @@ TLFEA_API int tlfea_batch_autotune(tlfea_batch_t b, const double* d_q, const dou
                                    double* d_f, double* d_vals, int32_t reps, void* stream,
                                    tlfea_gather_shape* chosen, float* ms_per_call) {
   if (!b || !d_q || !d_h || !d_f || !d_vals) return TLFEA_ERR_INVALID;
+  if (!batch_current(b)) return TLFEA_ERR_INVALID;
   if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
   const auto s = (hipStream_t)stream;
   const tlfea::GatherTuning current = b->tune;

@@ -168,6 +168,19 @@ __device__ __forceinline__ void tile_kinematics(const AsmArgs& a, const double* 
     }
 }
 
+// material constants of a launch: the host copy, or the device vector when given
+__device__ __forceinline__ MatParams launch_material(const AsmArgs& a) {
+  MatParams mp = a.mp;
+  if (a.mp_dev) {
+    mp.c0 = a.mp_dev[0];
+    mp.c1 = a.mp_dev[1];
+    mp.c2 = a.mp_dev[2];
+    mp.eta = a.mp_dev[3];
+    mp.lam_v = a.mp_dev[4];
+  }
+  return mp;
+}
+
 // Hd = F - I and Fdot at point q of element ge (float64).
 template <class Rule>
 __device__ __forceinline__ void load_kinematics(const AsmArgs& a, int64_t ge, int q, double* Hd, double* Fd,
@@ -205,6 +218,7 @@ __device__ __forceinline__ AsmArgs body_args(const BatchArgs& b, const BatchBody
   a.alpha = b.h[bi];
   a.beta = 1.0;
   a.flags = b.flags;
+  a.mp_dev = nullptr;
   return a;
 }
 

@@ -137,7 +137,7 @@ void free_mesh(Mesh& m) {
   (void)hipFree(m.d_geo);
   (void)hipFree(m.d_escale);
   (void)hipFree(m.d_flags);
-  (void)hipFree(m.d_vjp_acc);
+  (void)hipFree(m.d_mp);
   (void)hipFree(m.d_row_off);
   (void)hipFree(m.d_cols);
   (void)hipFree(m.d_adj_off);
@@ -276,6 +276,7 @@ AsmArgs make_args(const Mesh& m, const double* q, const double* qdot, double* f,
   a.alpha = alpha;
   a.beta = beta;
   a.flags = m.d_flags;
+  a.mp_dev = nullptr;
   return a;
 }
 
@@ -359,7 +360,7 @@ TLFEA_API int tlfea_mesh_create(const tlfea_mesh_desc* d, tlfea_mesh_t* out) {
   if (hipMalloc(&m.d_conn, sizeof(int32_t) * (nconn > 0 ? nconn : 1)) != hipSuccess ||
       hipMalloc(&m.d_X, sizeof(double) * (m.n_dof > 0 ? m.n_dof : 1)) != hipSuccess ||
       hipMalloc(&m.d_flags, sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc(&m.d_vjp_acc, sizeof(double) * 5) != hipSuccess ||
+      hipMalloc(&m.d_mp, sizeof(double) * 5) != hipSuccess ||
       (m.mc == 4 && hipMalloc(&m.d_escale, sizeof(double) * 2 * (m.n_elem > 0 ? m.n_elem : 1)) != hipSuccess)) {
     (void)hipGetLastError();
     return fail(TLFEA_ERR_NOMEM);
@@ -409,11 +410,13 @@ TLFEA_API int tlfea_mesh_set_material(tlfea_mesh_t mesh, int32_t material, const
   m.kv_eta = kv_eta;
   m.kv_lambda = kv_lambda;
   m.mp = tlfea::make_params(material, params, kv_eta, kv_lambda);
+  ++m.generation;
   return TLFEA_OK;
 }
 
 TLFEA_API int tlfea_mesh_set_precision(tlfea_mesh_t mesh, int32_t precision) {
   if (!mesh || (precision != TLFEA_FP64 && precision != TLFEA_MIXED)) return TLFEA_ERR_INVALID;
+  if (mesh->m.precision != precision) ++mesh->m.generation;
   mesh->m.precision = precision;
   return TLFEA_OK;
 }
@@ -421,6 +424,7 @@ TLFEA_API int tlfea_mesh_set_precision(tlfea_mesh_t mesh, int32_t precision) {
 TLFEA_API int tlfea_build_csr_pattern(tlfea_mesh_t mesh, int64_t* nnz_out) {
   if (!mesh) return TLFEA_ERR_INVALID;
   if (hipSetDevice(mesh->m.device) != hipSuccess) return TLFEA_ERR_HIP;
+  ++mesh->m.generation;  // the old pattern's arrays are released even when the build fails
   int rc = tlfea::build_pattern(mesh->m);
   if (rc) return rc;
   if (nnz_out) *nnz_out = mesh->m.nnz;
@@ -596,6 +600,30 @@ TLFEA_API int tlfea_internal_force_vjp(tlfea_mesh_t mesh, const double* d_q, con
   if (!mesh->m.has_pattern) return TLFEA_ERR_NO_PATTERN;
   mesh->m.last_stream = (hipStream_t)stream;
   return tlfea::launch_vjp(mesh->m, d_q, d_qdot, d_w, d_gq, d_gqdot, d_gparam, (hipStream_t)stream);
+}
+
+TLFEA_API int tlfea_internal_force_p(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot,
+                                     const double* d_params, double* d_f, void* stream) {
+  int rc = tlfea::check_call(mesh, d_q, true);
+  if (rc) return rc;
+  if (!d_params || !d_f) return TLFEA_ERR_INVALID;
+  Mesh& m = mesh->m;
+  auto s = (hipStream_t)stream;
+  m.last_stream = s;
+  if ((rc = tlfea::launch_params(m, d_params, s))) return rc;
+  tlfea::AsmArgs a = tlfea::make_args(m, d_q, d_qdot, nullptr, nullptr, 1.0, 0.0);
+  a.mp_dev = m.d_mp;
+  return tlfea::launch_force_blocks(m, a, d_f, s);
+}
+
+TLFEA_API int tlfea_internal_force_vjp_p(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot,
+                                         const double* d_params, const double* d_w, double* d_gq, double* d_gqdot,
+                                         double* d_gparam, void* stream) {
+  int rc = tlfea::check_call(mesh, d_q, true);
+  if (rc) return rc;
+  if (!d_params || !d_w || (!d_gq && !d_gqdot && !d_gparam)) return TLFEA_ERR_INVALID;
+  mesh->m.last_stream = (hipStream_t)stream;
+  return tlfea::launch_vjp(mesh->m, d_q, d_qdot, d_w, d_gq, d_gqdot, d_gparam, (hipStream_t)stream, d_params);
 }
 
 TLFEA_API int tlfea_get_runtime_flags(tlfea_mesh_t mesh, uint32_t* flags) {

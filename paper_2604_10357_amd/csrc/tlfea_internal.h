@@ -131,6 +131,8 @@ int autotune_shape(const GatherTuning& current, Apply&& apply, Run&& run, int re
 
 // Per-mesh state.  All d_* members are device allocations owned by the mesh.
 struct Mesh {
+  // bumped by every change a batch snapshots (pattern rebuild, material, precision)
+  uint64_t generation = 0;
   int device = 0;
   int elem_type = 0;
   int n_en = 0;        // shape functions (coefficient vectors) per element
@@ -153,7 +155,7 @@ struct Mesh {
   bool affine = false;            // true: one record per element; false: per (element, qp)
   double* d_escale = nullptr;     // ANCF: per element {lx/2, ly/2} (shell) or {L, W/2} (beam)
   uint32_t* d_flags = nullptr;    // runtime flags
-  double* d_vjp_acc = nullptr;    // 5 partial sums of the parameter VJP
+  double* d_mp = nullptr;         // 5 material constants converted from a device parameter vector
 
   // pass-2 work partition: node ranges whose CSR rows form one contiguous segment
   int32_t* d_inc_off = nullptr;   // n_pnodes + 1, node -> incident elements
@@ -188,7 +190,7 @@ struct Mesh {
   int32_t* d_cols_u = nullptr;
   int64_t nnz_u = -1;
   double density = 0.0;           // of the mass above (0: not built)
-  double* d_solver = nullptr;     // first-order solver: iteration counter, norm partials, norms
+  double* d_solver = nullptr;     // first-order solver: iteration counter, bias corrections, norm partials, norms
   double* d_dv = nullptr;         // gradient: v - v_prev per DOF (allocated by the first call)
   hipStream_t last_stream = nullptr;
 };
@@ -210,6 +212,7 @@ struct AsmArgs {
   const int32_t* row_off;
   const uint8_t* rank;
   MatParams mp;
+  const double* mp_dev;  // non-null: c0, c1, c2, eta, lam_v read from here instead of mp
   double alpha, beta;
   uint32_t* flags;
 };
@@ -332,10 +335,15 @@ int launch_block_sum(const Mesh& m, const double* blk, double* out, hipStream_t 
 constexpr size_t kNoallocScratchBytes = TLFEA_NOALLOC_SCRATCH_BYTES;
 size_t noalloc_force_bytes(const Mesh& m);
 int launch_force_noalloc(const Mesh& m, const AsmArgs& a, double* f, hipStream_t s);
+// the force-block path with the mesh's work buffer (force only, pattern needed)
+int launch_force_blocks(Mesh& m, const AsmArgs& a, double* f, hipStream_t s);
+// material constants of a device parameter vector (p0, p1, p2, kv_eta, kv_lambda) -> m.d_mp
+int launch_params(const Mesh& m, const double* d_params, hipStream_t s);
 
 // VJP (vjp.hip)
 int launch_vjp(Mesh& m, const double* q, const double* qdot, const double* w, double* gq,
-               double* gqdot, double* gparam, hipStream_t s);
+               double* gqdot, double* gparam, hipStream_t s,
+               const double* d_params = nullptr);
 
 AsmArgs make_args(const Mesh& m, const double* q, const double* qdot, double* f, double* vals,
                   double alpha, double beta);

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_elem(AsmArgs a, const doubl
   __syncthreads();  // the nodal values are consumed: the LDS holds Zhat from here on
   const double dV = det * Rule::w_rt(q);
   double Zq[9], Zd[9], part[5];
-  stress_vjp(a.mp, Hd, Fd, Wg, Zq, Zd, part);
+  stress_vjp(launch_material(a), Hd, Fd, Wg, Zq, Zd, part);
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
     Zq[t] *= dV;
@@ -156,7 +156,8 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_elem(AsmArgs a, const doubl
 // internal partials (c0, c1, c2, eta, lam_v), summed over the workgroups in a
 // fixed order, -> user parameters
 __global__ __launch_bounds__(256) void k_vjp_finalize(const double* __restrict__ gpart, int64_t n_blocks, int kind,
-                                                      double E, double nu, double* gparam) {
+                                                      double E, double nu, const double* __restrict__ d_params,
+                                                      double* gparam) {
   __shared__ double red[256][5];
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t b = threadIdx.x; b < n_blocks; b += 256)
@@ -173,6 +174,10 @@ __global__ __launch_bounds__(256) void k_vjp_finalize(const double* __restrict__
   }
   if (threadIdx.x != 0) return;
   const double* g = red[0];
+  if (d_params) {
+    E = d_params[0];
+    nu = d_params[1];
+  }
   if (kind == 1) {
     const double dlam_dE = nu / ((1 + nu) * (1 - 2 * nu)), dmu_dE = 1.0 / (2 * (1 + nu));
     const double dlam_dnu = E * (1 + 2 * nu * nu) / ((1 + nu) * (1 + nu) * (1 - 2 * nu) * (1 - 2 * nu));
@@ -209,9 +214,13 @@ int launch_vjp_elem(const AsmArgs& a, const double* w, const int32_t* incpos, do
 }  // namespace
 
 int launch_vjp(Mesh& m, const double* q, const double* qdot, const double* w, double* gq, double* gqdot,
-               double* gparam, hipStream_t s) {
+               double* gparam, hipStream_t s, const double* d_params) {
   if (!m.d_incpos) return TLFEA_ERR_NO_PATTERN;
   AsmArgs a = make_args(m, q, qdot, nullptr, nullptr, 1.0, 0.0);
+  if (d_params) {
+    if (int rc = launch_params(m, d_params, s)) return rc;
+    a.mp_dev = m.d_mp;
+  }
   int64_t blocks;
   if (m.elem_type == TLFEA_T10) blocks = vjp_blocks<RuleT10>(m.n_elem);
   else if (m.elem_type == TLFEA_ANCF3243) blocks = vjp_blocks<RuleBeam>(m.n_elem);
@@ -236,7 +245,7 @@ int launch_vjp(Mesh& m, const double* q, const double* qdot, const double* w, do
   if (gqdot && (rc = launch_block_sum(m, bqd, gqdot, s))) return rc;
   if (gparam) {
     hipLaunchKernelGGL(k_vjp_finalize, dim3(1), dim3(256), 0, s, gpart, blocks, m.material, m.params[0],
-                       m.params[1], gparam);
+                       m.params[1], d_params, gparam);
     TLFEA_HIP_CHECK(hipGetLastError());
   }
   return TLFEA_OK;

@@ -52,7 +52,8 @@ def test_adamw_matches_oracle(precision, kind):
     eg = rel_err(g.cpu().numpy(), g_ref)[0]
     eq = rel_err(q.cpu().numpy() - wl.q, q_ref - wl.q)[0]
     print(f"  v {ev:.2e}  g {eg:.2e}  q {eq:.2e}", flush=True)
-    tol = 1e-9 if precision == "fp64" else 1e-5
+    # FP64: the stated 1e-12 bar (measured ~5e-14 on 25 iterations)
+    tol = 1e-12 if precision == "fp64" else 1e-5
     assert ev <= tol and eq <= tol and eg <= tol
     assert abs(gnorm - np.linalg.norm(g_ref)) <= tol * np.linalg.norm(g_ref)
     m.close()

@@ -462,9 +462,22 @@ def bench_batched(args, torch):
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
         tuning = autotune(args, b, lambda: b.autotune(q, qd, hs, f, vals, reps=5))
+        tuning["schedule"] = b.schedule()
         for _ in range(args.warmup):
             b.assemble(q, qd, hs, f, vals)
         ms = time_calls(lambda: b.assemble(q, qd, hs, f, vals), args.steps, torch)
+        # every schedule at the tuned shape, for the record
+        kept = b.schedule()
+        sched_ms = {}
+        for name, pers, te in (("per_item", False, 25), ("persistent_lpt_25", True, 25), ("persistent_lpt_16", True, 16)):
+            if pers and args.precision != "mixed":
+                continue
+            b.set_schedule(pers, te)
+            for _ in range(args.warmup):
+                b.assemble(q, qd, hs, f, vals)
+            sched_ms[name] = time_calls(lambda: b.assemble(q, qd, hs, f, vals), args.steps, torch)
+        b.set_schedule(bool(kept["persistent"]), kept["tile_elems"])
+        tuning["schedules_ms"] = sched_ms
         for _ in range(args.warmup):
             b.assemble(q, qd, hs, f, vals, loop=True)
         ms_loop = time_calls(lambda: b.assemble(q, qd, hs, f, vals, loop=True), args.steps, torch)
@@ -480,7 +493,9 @@ def bench_batched(args, torch):
         "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ("k_elem_rows_batch + k_gather_rows_batch (one graph)" if args.precision == "mixed"
+                     "kernel": (("k_elem_rows_batch_lpt + k_gather_rows_batch_lpt (persistent, one graph)"
+                                 if tuning["schedule"]["persistent"] else
+                                 "k_elem_rows_batch + k_gather_rows_batch (one graph)") if args.precision == "mixed"
                                 else "k_stage_batch + k_gather_batch (one graph)"), "kernel_ms": ms,
                      "algorithmic_bytes": B},
         "per_body_loop": {"ms_per_step": ms_loop, "value": n_el / (ms_loop * 1e-3),

@@ -431,13 +431,32 @@ int tlfea_batch_assemble(tlfea_batch_t batch, const double* d_q, const double* d
 int tlfea_batch_assemble_loop(tlfea_batch_t batch, const double* d_q, const double* d_qdot,
                               const double* d_h, double* d_f, double* d_vals, void* stream);
 
+/* Schedule of the batched element-row launches (T10 bodies in mixed
+ * precision; the benchmark spec's persistent batched form).  persistent = 0: one
+ * workgroup per element tile and per node range (the default).  persistent =
+ * 1: grids of as many workgroups as the GPU holds at once, which take work
+ * items from device counters: tiles of tile_elems (25 or 16) elements, full
+ * tiles of the largest bodies first and partial tiles last, then node ranges
+ * by decreasing work (longest-processing-time order).  Either schedule gives
+ * the same results up to rounding order.  TLFEA_ERR_UNSUPPORTED for a batch
+ * off the element-row path.  get: grid_tiles / grid_ranges receive the
+ * workgroups launched per pass (any pointer may be NULL). */
+int tlfea_batch_set_schedule(tlfea_batch_t batch, int32_t persistent, int32_t tile_elems);
+int tlfea_batch_get_schedule(tlfea_batch_t batch, int32_t* persistent, int32_t* tile_elems, int32_t* grid_tiles,
+                             int32_t* grid_ranges);
+
 /* The batch's own pass-2 launch shape (the bodies' shapes are not changed):
  * set, get and autotune as for a mesh, over the concatenated ranges of all
  * bodies.  The batch starts with the first body's shape.  A new shape drops
  * the captured graph of tlfea_batch_assemble (it is captured again at the
  * next call).  tlfea_batch_autotune times the uncaptured launch pair of
- * tlfea_batch_assemble on `stream` and leaves the fastest shape's result in
- * d_f / d_vals. */
+ * tlfea_batch_assemble on `stream` over every schedule (both forms above; on
+ * the element-row path the persistent one with both tile sizes) and every
+ * candidate shape, keeps the fastest (a change of schedule must gain at least
+ * 5 %), and leaves its result in d_f / d_vals.  The choice is remembered for
+ * the life of the process under the batch's signature (element type,
+ * precision and every body's element and node counts): a batch created later
+ * with the same signature starts with it. */
 int tlfea_batch_set_gather_shape(tlfea_batch_t batch, const tlfea_gather_shape* shape);
 int tlfea_batch_get_gather_shape(tlfea_batch_t batch, tlfea_gather_shape* shape, int64_t* n_ranges);
 int tlfea_batch_autotune(tlfea_batch_t batch, const double* d_q, const double* d_qdot, const double* d_h,

@@ -30,6 +30,7 @@ EXPORTED = [
     "tlfea_batch_destroy", "tlfea_batch_offsets", "tlfea_batch_assemble", "tlfea_batch_assemble_loop",
     "tlfea_mesh_set_gather_shape", "tlfea_mesh_get_gather_shape", "tlfea_mesh_autotune",
     "tlfea_batch_set_gather_shape", "tlfea_batch_get_gather_shape", "tlfea_batch_autotune",
+    "tlfea_batch_set_schedule", "tlfea_batch_get_schedule",
     "tlfea_build_mass", "tlfea_get_mass", "tlfea_assemble_newton", "tlfea_assemble_newton_upper",
     "tlfea_newton_gradient",
     "tlfea_build_upper_pattern", "tlfea_get_csr_pattern_upper", "tlfea_assemble_upper", "tlfea_adamw_solve",
@@ -119,6 +120,8 @@ def lib() -> ctypes.CDLL:
         "tlfea_mesh_autotune": ([vp, vp, vp, dbl, vp, vp, i32, vp, P(GatherShape), P(ctypes.c_float)], ctypes.c_int),
         "tlfea_batch_set_gather_shape": ([vp, P(GatherShape)], ctypes.c_int),
         "tlfea_batch_get_gather_shape": ([vp, P(GatherShape), P(i64)], ctypes.c_int),
+        "tlfea_batch_set_schedule": ([vp, i32, i32], ctypes.c_int),
+        "tlfea_batch_get_schedule": ([vp, P(i32), P(i32), P(i32), P(i32)], ctypes.c_int),
         "tlfea_batch_autotune": ([vp, vp, vp, vp, vp, vp, i32, vp, P(GatherShape), P(ctypes.c_float)], ctypes.c_int),
         "tlfea_build_mass": ([vp, dbl], ctypes.c_int),
         "tlfea_get_mass": ([vp, vp, vp], ctypes.c_int),

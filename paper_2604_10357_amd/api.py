@@ -373,9 +373,21 @@ class TLBatch:
                 "tlfea_batch_get_gather_shape")
         return sh.as_dict(), n.value
 
+    def set_schedule(self, persistent: bool, tile_elems: int = 25):
+        """Persistent LPT schedule (tiles of tile_elems elements) or one workgroup per item."""
+        N.check(N.lib().tlfea_batch_set_schedule(self._h, int(bool(persistent)), int(tile_elems)),
+                "tlfea_batch_set_schedule")
+
+    def schedule(self):
+        """dict(persistent, tile_elems, grid_tiles, grid_ranges)"""
+        v = [ctypes.c_int32() for _ in range(4)]
+        N.check(N.lib().tlfea_batch_get_schedule(self._h, *[ctypes.byref(x) for x in v]), "tlfea_batch_get_schedule")
+        return dict(zip(("persistent", "tile_elems", "grid_tiles", "grid_ranges"), [x.value for x in v]))
+
     def autotune(self, q, qdot, h, f=None, vals=None, reps: int = 5):
-        """Times the launch-shape grid on the batched launch pair and keeps the fastest;
-        returns (shape dict, ms per call, f, vals) with f / vals holding its result."""
+        """Times every schedule and launch shape on the batched launch pair and keeps the
+        fastest; returns (shape dict, ms per call, f, vals) with f / vals holding its result
+        (schedule() tells the schedule kept)."""
         nd, nz = self.dof_off[-1], self.nnz_off[-1]
         f = torch.empty(nd, dtype=torch.float64, device=q.device) if f is None else f
         vals = torch.empty(nz, dtype=torch.float64, device=q.device) if vals is None else vals

@@ -669,21 +669,21 @@ constexpr int kDnL = 20;          // LDS stride of a node's gradient row (16 use
                                   // of the ten nodes on different banks)
 constexpr int kStgL = 100;        // LDS stride of a staged row block (96 used; spreads the banks)
 
-template <class Rule>
+template <class Rule, int EB = kRowElems>
 __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* __restrict__ incpos,
                                                float* __restrict__ rows, int64_t blk) {
   static_assert(Rule::MC == 1 && Rule::NEN == 10, "element rows are built for T10");
   constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN;
-  static_assert(kRowElems * NQ <= kRowThreads, "a lane per point");
+  static_assert(EB * NQ <= kRowThreads, "a lane per point");
   static_assert(kRowThreads % 64 == 0 && 9 * kRowStage <= 64, "a wave stages whole incidences");
-  __shared__ __align__(16) float rec[kRowElems * NQ * kRecL];
+  __shared__ __align__(16) float rec[EB * NQ * kRecL];
   __shared__ __align__(16) float dn[NEN * kDnL];  // parent gradients of every node at every point
-  __shared__ int32_t pos[kRowElems * NEN];         // incidence position of every (element, node)
+  __shared__ int32_t pos[EB * NEN];         // incidence position of every (element, node)
   __shared__ __align__(16) float stage_buf[(kRowThreads / 64) * kRowStage * kStgL];  // per-wave row blocks
-  static_assert(kRowElems * NEN * 6 * sizeof(double) <= sizeof(rec), "nodal values fit the record area");
+  static_assert(EB * NEN * 6 * sizeof(double) <= sizeof(rec), "nodal values fit the record area");
   const int tid = threadIdx.x;
-  const int64_t e0 = blk * kRowElems;
-  const int ne = (int)(a.n_elem - e0 < kRowElems ? a.n_elem - e0 : kRowElems);
+  const int64_t e0 = blk * EB;
+  const int ne = (int)(a.n_elem - e0 < EB ? a.n_elem - e0 : EB);
   // 1. nodal values, the tables of the tasks, then each point's kinematics
   double* nod = reinterpret_cast<double*>(rec);
   gather_nodal<Rule>(a, e0, ne, nod);
@@ -803,6 +803,31 @@ __global__ __launch_bounds__(kRowThreads) void k_elem_rows_batch(BatchArgs b) {
   elem_rows_tile<Rule>(a, B.incpos, (float*)b.stage + B.blk_inc_off * kRowBlk, blk - B.rblock_off);
 }
 
+// Persistent form of the batch (the LPT schedule): a grid sized to what the
+// GPU holds at once, whose workgroups take (body, tile) items from a counter
+// in a list ordered longest first (full tiles of the largest bodies first,
+// partial tiles last), EB elements per tile.
+template <class Rule, int EB>
+__global__ __launch_bounds__(kRowThreads) void k_elem_rows_batch_lpt(BatchArgs b, const int2* __restrict__ items,
+                                                                    int n_items, unsigned* __restrict__ counter) {
+  __shared__ int item;
+  for (;;) {
+    __syncthreads();  // the previous item's LDS and its item index are consumed
+    if (threadIdx.x == 0) item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int it = item;
+    if (it >= n_items) return;  // every wave of the workgroup leaves here together
+    const int2 t = items[it];
+    const BatchBody& B = b.bodies[t.x];
+    const AsmArgs a = body_args(b, B, t.x);
+    elem_rows_tile<Rule, EB>(a, B.incpos, (float*)b.stage + B.blk_inc_off * kRowBlk, t.y);
+  }
+}
+
+__global__ void k_reset_counters(unsigned* counters) {
+  if (threadIdx.x < 2) counters[threadIdx.x] = 0u;
+}
+
 // Pass 2 over the row blocks: a lane per (incidence, row i, component k) task
 // of the range loads its ten K entries (three aligned 16-byte pieces of the
 // block, shifted by 2 values for odd slots) and adds them into the range's
@@ -888,6 +913,33 @@ __global__ __launch_bounds__(512) void k_gather_rows_batch(BatchArgs b) {
   g.vals = b.vals + B.nnz_off;
   g.inc_cap = b.inc_cap;
   gather_rows<true, true, false>(g, br.I0, br.I1, smem, pre, rowo);
+}
+
+// persistent form: ranges taken from a counter, largest first
+__global__ __launch_bounds__(512) void k_gather_rows_batch_lpt(BatchArgs b, const int32_t* __restrict__ order,
+                                                               int n_items, unsigned* __restrict__ counter) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t pre[kMaxRangeNodes + 1];
+  __shared__ int32_t rowo[kMaxRangeNodes * 3];
+  __shared__ int item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int it = item;
+    if (it >= n_items) return;
+    const BatchRange br = b.ranges[order[it]];
+    const BatchBody& B = b.bodies[br.body];
+    GatherArgs g{};
+    g.inc_off = B.inc_off;
+    g.row_off = B.row_off;
+    g.rank = B.rank_inc;
+    g.stage = (const float*)b.stage + B.blk_inc_off * kRowBlk;
+    g.f = b.f + B.dof_off;
+    g.vals = b.vals + B.nnz_off;
+    g.inc_cap = b.inc_cap;
+    gather_rows<true, true, false>(g, br.I0, br.I1, smem, pre, rowo);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1458,6 +1510,24 @@ size_t stage_record_bytes(int precision) {
   return (size_t)kRecK * (precision == TLFEA_MIXED ? sizeof(float) : sizeof(double));
 }
 
+// Workgroups of the persistent batch kernels one CU holds at once (tile kernel
+// for EB elements per tile; range kernel for the given shape and LDS bytes).
+int batch_lpt_occupancy(int tile_elems, int waves, size_t lds_all, int* tiles_per_cu, int* ranges_per_cu) {
+  int nt = 0, nr = 0;
+  if (tile_elems == 16)
+    TLFEA_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nt, reinterpret_cast<const void*>(k_elem_rows_batch_lpt<RuleT10, 16>), kRowThreads, 0));
+  else
+    TLFEA_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nt, reinterpret_cast<const void*>(k_elem_rows_batch_lpt<RuleT10, kRowElems>), kRowThreads, 0));
+  if (int rc = allow_lds(k_gather_rows_batch_lpt, lds_all)) return rc;
+  TLFEA_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &nr, reinterpret_cast<const void*>(k_gather_rows_batch_lpt), 64 * waves, lds_all));
+  *tiles_per_cu = std::max(nt, 1);
+  *ranges_per_cu = std::max(nr, 1);
+  return TLFEA_OK;
+}
+
 int launch_zero(double* p, int64_t n, hipStream_t s) {
   if (n <= 0) return TLFEA_OK;
   int64_t blocks = (n + 255) / 256;
@@ -1585,8 +1655,26 @@ int launch_block_sum(const Mesh& m, const double* blk, double* out, hipStream_t 
 }
 
 int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tu, const BatchArgs& b,
-                 int n_ranges, size_t lds, hipStream_t s) {
+                 int n_ranges, size_t lds, hipStream_t s, const BatchSchedule& sc) {
   if (n_ranges == 0) return TLFEA_OK;
+  if (b.rows && sc.persistent) {
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, sc.counters);
+    if (sc.n_tiles > 0) {
+      if (sc.tile_elems == 16)
+        hipLaunchKernelGGL((k_elem_rows_batch_lpt<RuleT10, 16>), dim3(sc.grid_tiles), dim3(kRowThreads), 0, s, b,
+                           sc.tiles, sc.n_tiles, sc.counters);
+      else
+        hipLaunchKernelGGL((k_elem_rows_batch_lpt<RuleT10, kRowElems>), dim3(sc.grid_tiles), dim3(kRowThreads), 0, s,
+                           b, sc.tiles, sc.n_tiles, sc.counters);
+    }
+    TLFEA_HIP_CHECK(hipGetLastError());
+    const size_t lds_all = lds + b.inc_cap;
+    if (int rc = allow_lds(k_gather_rows_batch_lpt, lds_all)) return rc;
+    hipLaunchKernelGGL(k_gather_rows_batch_lpt, dim3(sc.grid_ranges), dim3(64 * tu.waves), lds_all, s, b,
+                       sc.range_order, n_ranges, sc.counters + 1);
+    TLFEA_HIP_CHECK(hipGetLastError());
+    return TLFEA_OK;
+  }
   if (b.rows) {
     if (b.n_rblocks > 0)
       hipLaunchKernelGGL(k_elem_rows_batch<RuleT10>, dim3((unsigned)b.n_rblocks), dim3(kRowThreads), 0, s, b);

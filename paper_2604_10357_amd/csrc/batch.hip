@@ -9,6 +9,8 @@
 // two launches are captured once into a HIP graph and replayed while the
 // argument pointers stay the same.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -36,6 +38,14 @@ struct tlfea_batch_s {
   int inc_cap = 0;
   void* d_stage = nullptr;
   uint32_t* d_flags = nullptr;
+  // schedule of the element-row launches (persistent LPT form or one workgroup per item)
+  tlfea::BatchSchedule sched;
+  std::vector<BatchRange> h_ranges;  // the current range cut, host copy
+  int2* d_tiles = nullptr;
+  int32_t* d_range_order = nullptr;
+  size_t tiles_cap = 0, order_cap = 0;
+  unsigned* d_counters = nullptr;
+  uint64_t signature = 0;  // of the member sizes, element type and precision (autotuner cache key)
   // graph cache, keyed by the argument pointers and the stream
   hipGraphExec_t exec = nullptr;
   const void* key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -53,7 +63,96 @@ static void batch_free(tlfea_batch_s* b) {
   (void)hipFree(b->d_ranges);
   (void)hipFree(b->d_stage);
   (void)hipFree(b->d_flags);
+  (void)hipFree(b->d_tiles);
+  (void)hipFree(b->d_range_order);
+  (void)hipFree(b->d_counters);
   delete b;
+}
+
+template <typename T>
+static int upload(T*& d, size_t& cap, const std::vector<T>& h) {
+  if (h.size() > cap || !d) {
+    if (d && hipDeviceSynchronize() != hipSuccess) return TLFEA_ERR_HIP;  // queued work may read the old list
+    T* nd = nullptr;
+    if (hipMalloc(&nd, sizeof(T) * std::max<size_t>(1, h.size())) != hipSuccess) {
+      (void)hipGetLastError();
+      return TLFEA_ERR_NOMEM;
+    }
+    (void)hipFree(d);
+    d = nd;
+    cap = std::max<size_t>(1, h.size());
+  } else if (hipDeviceSynchronize() != hipSuccess) {
+    return TLFEA_ERR_HIP;
+  }
+  if (!h.empty() && hipMemcpy(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return TLFEA_ERR_HIP;
+  return TLFEA_OK;
+}
+
+// The persistent (LPT) schedule of the element-row batch: every body's tiles of
+// tile_elems elements, full tiles of the largest bodies first and partial tiles
+// last; the ranges by decreasing work (incidences, then rows); grids of as
+// many workgroups as the GPU holds at once.
+static int batch_plan_lpt(tlfea_batch_s* b, int tile_elems) {
+  if (!b->rows) return TLFEA_ERR_UNSUPPORTED;
+  if (tile_elems != 16 && tile_elems != tlfea::row_elems()) return TLFEA_ERR_INVALID;
+  struct Tile {
+    int64_t work, body_size;
+    int body, tile;
+  };
+  std::vector<Tile> tiles;
+  for (size_t i = 0; i < b->meshes.size(); ++i) {
+    const int64_t ne = b->meshes[i]->m.n_elem;
+    for (int64_t t = 0; t * tile_elems < ne; ++t)
+      tiles.push_back(Tile{std::min<int64_t>(tile_elems, ne - t * tile_elems), ne, (int)i, (int)t});
+  }
+  if (tiles.size() > (size_t)INT32_MAX) return TLFEA_ERR_TOO_LARGE;
+  std::stable_sort(tiles.begin(), tiles.end(), [](const Tile& x, const Tile& y) {
+    return x.work != y.work ? x.work > y.work : x.body_size > y.body_size;
+  });
+  std::vector<int2> items(tiles.size());
+  for (size_t k = 0; k < tiles.size(); ++k) items[k] = int2{tiles[k].body, tiles[k].tile};
+  std::vector<int64_t> work(b->h_ranges.size());
+  for (size_t r = 0; r < b->h_ranges.size(); ++r) {
+    const BatchRange& br = b->h_ranges[r];
+    const tlfea::Mesh& m = b->meshes[br.body]->m;
+    work[r] = 16 * (int64_t)(m.h_inc_off[br.I1] - m.h_inc_off[br.I0]) + (br.I1 - br.I0);
+  }
+  std::vector<int32_t> order(b->h_ranges.size());
+  for (size_t r = 0; r < order.size(); ++r) order[r] = (int32_t)r;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work[x] > work[y]; });
+  if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
+  int rc;
+  if ((rc = upload(b->d_tiles, b->tiles_cap, items)) || (rc = upload(b->d_range_order, b->order_cap, order)))
+    return rc;
+  if (!b->d_counters && hipMalloc(&b->d_counters, 2 * sizeof(unsigned)) != hipSuccess) {
+    (void)hipGetLastError();
+    return TLFEA_ERR_NOMEM;
+  }
+  int cus = 0, per_tile = 1, per_range = 1;
+  TLFEA_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+  if ((rc = tlfea::batch_lpt_occupancy(tile_elems, b->tune.waves, b->lds + b->inc_cap, &per_tile, &per_range)))
+    return rc;
+  tlfea::BatchSchedule& sc = b->sched;
+  sc.persistent = 1;
+  sc.tile_elems = tile_elems;
+  sc.tiles = b->d_tiles;
+  sc.n_tiles = (int)items.size();
+  sc.range_order = b->d_range_order;
+  sc.counters = b->d_counters;
+  sc.grid_tiles = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_tile, sc.n_tiles));
+  sc.grid_ranges = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_range, b->n_ranges));
+  drop_graph(b);
+  return TLFEA_OK;
+}
+
+static int batch_set_schedule(tlfea_batch_s* b, int persistent, int tile_elems) {
+  if (!persistent) {
+    b->sched = tlfea::BatchSchedule{};
+    drop_graph(b);
+    return TLFEA_OK;
+  }
+  return batch_plan_lpt(b, tile_elems);
 }
 
 // Cut every body's nodes into ranges for launch shape t and upload the
@@ -96,8 +195,36 @@ static int batch_set_shape(tlfea_batch_s* b, const tlfea::GatherTuning& t) {
   b->lds = sizeof(double) * (size_t)max_vals;
   b->inc_cap = inc_cap;
   b->tune = t;
+  b->h_ranges = std::move(ranges);
   drop_graph(b);  // the captured launches hold the old grid and LDS size
-  return TLFEA_OK;
+  return b->sched.persistent ? batch_plan_lpt(b, b->sched.tile_elems) : TLFEA_OK;
+}
+
+// Tuned choices of the autotuner, per batch signature, for the life of the process.
+struct TunedChoice {
+  tlfea::GatherTuning shape;
+  int persistent = 0, tile_elems = 25;
+};
+static std::mutex g_tuned_mu;
+static std::map<uint64_t, TunedChoice> g_tuned;
+
+static uint64_t batch_signature(const tlfea_batch_s* b) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the sizes that decide the launches
+  auto mix = [&](uint64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (v >> (8 * k)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)b->elem_type);
+  mix((uint64_t)b->gl0);
+  mix((uint64_t)b->precision);
+  mix((uint64_t)b->meshes.size());
+  for (const tlfea_mesh_t mh : b->meshes) {
+    mix((uint64_t)mh->m.n_elem);
+    mix((uint64_t)mh->m.n_pnodes);
+  }
+  return h;
 }
 
 TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, tlfea_batch_t* out) {
@@ -183,7 +310,20 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
     batch_free(b);
     return TLFEA_ERR_HIP;
   }
-  if (int rc = batch_set_shape(b, m0.tune)) {
+  b->signature = batch_signature(b);
+  TunedChoice choice;
+  bool tuned = false;
+  {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    auto it = g_tuned.find(b->signature);
+    if (it != g_tuned.end()) {
+      choice = it->second;
+      tuned = true;
+    }
+  }
+  int rc = batch_set_shape(b, tuned ? choice.shape : m0.tune);
+  if (!rc && tuned && choice.persistent) rc = batch_set_schedule(b, 1, choice.tile_elems);
+  if (rc) {
     batch_free(b);
     return rc;
   }
@@ -236,7 +376,7 @@ static BatchArgs batch_args(tlfea_batch_t b, const double* d_q, const double* d_
 }
 
 static int batch_enqueue(tlfea_batch_t b, const BatchArgs& a, hipStream_t s) {
-  return tlfea::launch_batch(b->elem_type, b->gl0, b->precision, b->tune, a, b->n_ranges, b->lds, s);
+  return tlfea::launch_batch(b->elem_type, b->gl0, b->precision, b->tune, a, b->n_ranges, b->lds, s, b->sched);
 }
 
 TLFEA_API int tlfea_batch_assemble(tlfea_batch_t b, const double* d_q, const double* d_qdot, const double* d_h,
@@ -310,6 +450,25 @@ TLFEA_API int tlfea_batch_get_gather_shape(tlfea_batch_t b, tlfea_gather_shape* 
   return TLFEA_OK;
 }
 
+TLFEA_API int tlfea_batch_set_schedule(tlfea_batch_t b, int32_t persistent, int32_t tile_elems) {
+  if (!b || (persistent != 0 && persistent != 1)) return TLFEA_ERR_INVALID;
+  if (!batch_current(b)) return TLFEA_ERR_INVALID;
+  if (persistent && !b->rows) return TLFEA_ERR_UNSUPPORTED;
+  if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
+  return batch_set_schedule(b, persistent, tile_elems);
+}
+
+TLFEA_API int tlfea_batch_get_schedule(tlfea_batch_t b, int32_t* persistent, int32_t* tile_elems,
+                                       int32_t* grid_tiles, int32_t* grid_ranges) {
+  if (!b) return TLFEA_ERR_INVALID;
+  const tlfea::BatchSchedule& sc = b->sched;
+  if (persistent) *persistent = sc.persistent;
+  if (tile_elems) *tile_elems = sc.persistent ? sc.tile_elems : tlfea::row_elems();
+  if (grid_tiles) *grid_tiles = sc.persistent ? sc.grid_tiles : (int32_t)b->n_rblocks;
+  if (grid_ranges) *grid_ranges = sc.persistent ? sc.grid_ranges : b->n_ranges;
+  return TLFEA_OK;
+}
+
 TLFEA_API int tlfea_batch_autotune(tlfea_batch_t b, const double* d_q, const double* d_qdot, const double* d_h,
                                    double* d_f, double* d_vals, int32_t reps, void* stream,
                                    tlfea_gather_shape* chosen, float* ms_per_call) {
@@ -317,19 +476,63 @@ TLFEA_API int tlfea_batch_autotune(tlfea_batch_t b, const double* d_q, const dou
   if (!batch_current(b)) return TLFEA_ERR_INVALID;
   if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
   const auto s = (hipStream_t)stream;
-  const tlfea::GatherTuning current = b->tune;
-  tlfea::GatherTuning best = current;
-  float ms = 0.0f;
-  // the launch pair itself, uncaptured: shapes change between the timings
-  const int rc = tlfea::autotune_shape(
-      current, [&](const tlfea::GatherTuning& t) { return batch_set_shape(b, t); },
-      [&]() { return batch_enqueue(b, batch_args(b, d_q, d_qdot, d_h, d_f, d_vals), s); }, reps, s, best, ms);
-  if (rc) return rc;
-  if (chosen) {
-    chosen->waves = best.waves;
-    chosen->range_tasks = best.range_tasks;
-    chosen->range_values = best.range_values;
+  // schedules: one workgroup per item; on the element-row path also the
+  // persistent LPT form with tiles of 25 and of 16 elements
+  struct Cand {
+    int persistent, tile_elems;
+  };
+  std::vector<Cand> cands{{0, tlfea::row_elems()}};
+  if (b->rows) {
+    cands.push_back({1, tlfea::row_elems()});
+    cands.push_back({1, 16});
   }
-  if (ms_per_call) *ms_per_call = ms;
+  const Cand cur{b->sched.persistent, b->sched.persistent ? b->sched.tile_elems : tlfea::row_elems()};
+  const tlfea::GatherTuning cur_shape = b->tune;
+  TunedChoice best, at_cur;
+  float best_ms = -1.0f, cur_ms = -1.0f;
+  for (const Cand& c : cands) {
+    int rc = batch_set_shape(b, cur_shape);
+    if (!rc) rc = batch_set_schedule(b, c.persistent, c.tile_elems);
+    if (rc == TLFEA_ERR_UNSUPPORTED) continue;
+    if (rc) return rc;
+    tlfea::GatherTuning shape = cur_shape;
+    float ms = 0.0f;
+    // the launch pair itself, uncaptured: shapes change between the timings
+    rc = tlfea::autotune_shape(
+        cur_shape, [&](const tlfea::GatherTuning& t) { return batch_set_shape(b, t); },
+        [&]() { return batch_enqueue(b, batch_args(b, d_q, d_qdot, d_h, d_f, d_vals), s); }, reps, s, shape, ms);
+    if (rc == TLFEA_ERR_UNSUPPORTED) continue;
+    if (rc) return rc;
+    if (c.persistent == cur.persistent && c.tile_elems == cur.tile_elems) {
+      cur_ms = ms;
+      at_cur.shape = shape;
+      at_cur.persistent = c.persistent;
+      at_cur.tile_elems = c.tile_elems;
+    }
+    if (best_ms < 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best.shape = shape;
+      best.persistent = c.persistent;
+      best.tile_elems = c.tile_elems;
+    }
+  }
+  if (best_ms < 0.0f) return TLFEA_ERR_UNSUPPORTED;
+  if (cur_ms >= 0.0f && best_ms > (1.0f - tlfea::kTuneMargin) * cur_ms) {
+    best = at_cur;  // a schedule change must pay for itself
+    best_ms = cur_ms;
+  }
+  int rc = batch_set_shape(b, best.shape);
+  if (!rc) rc = batch_set_schedule(b, best.persistent, best.tile_elems);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    g_tuned[b->signature] = best;
+  }
+  if (chosen) {
+    chosen->waves = best.shape.waves;
+    chosen->range_tasks = best.shape.range_tasks;
+    chosen->range_values = best.shape.range_values;
+  }
+  if (ms_per_call) *ms_per_call = best_ms;
   return TLFEA_OK;
 }

@@ -281,6 +281,22 @@ struct BatchArgs {
   int inc_cap;  // LDS bytes for a range's incidence -> node table (multiple of 16)
 };
 
+// Schedule of a batched element-row launch.  persistent = 0: one workgroup per
+// tile and per range (bodies found by bisection).  persistent = 1: fixed grids
+// of grid_tiles / grid_ranges workgroups taking items from two device
+// counters, tiles of tile_elems elements listed longest first, ranges ordered
+// by decreasing work.
+struct BatchSchedule {
+  int persistent = 0;
+  int tile_elems = 25;
+  const int2* tiles = nullptr;
+  int n_tiles = 0;
+  const int32_t* range_order = nullptr;
+  unsigned* counters = nullptr;
+  int grid_tiles = 0, grid_ranges = 0;
+};
+int batch_lpt_occupancy(int tile_elems, int waves, size_t lds_all, int* tiles_per_cu, int* ranges_per_cu);
+
 MatParams make_params(int material, const double* params, double eta, double lam_v);
 
 // bytes of pass-1 records for a mesh / per record
@@ -297,7 +313,7 @@ size_t stage_record_bytes(int precision);
 size_t row_block_bytes();  // element-row path: bytes per (element, node) row block
 int row_elems();           // element-row path: elements per pass-1 workgroup
 int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tune, const BatchArgs& b,
-                 int n_ranges, size_t lds, hipStream_t s);
+                 int n_ranges, size_t lds, hipStream_t s, const BatchSchedule& sc);
 
 // kernel launchers (assemble.hip)
 int launch_zero(double* p, int64_t n, hipStream_t s);

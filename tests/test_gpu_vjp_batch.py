@@ -216,3 +216,72 @@ def test_batch_refuses_members_changed_after_creation():
         b.close()
         for m in meshes:
             m.close()
+
+
+@pytest.mark.parametrize("tile_elems", [25, 16])
+def test_batch_persistent_lpt_schedule(tile_elems):
+    """The persistent LPT schedule (work counters, longest items first) against
+    the oracle body by body and against the one-workgroup-per-item schedule,
+    over graph replays; the counters restart on every call."""
+    print(f"[gpu] batch persistent {tile_elems}", flush=True)
+    wls = batch_workloads(14, 41)
+    meshes = [make_mesh(wl, "mixed") for wl in wls]
+    b = TLBatch(meshes)
+    q = cuda(np.concatenate([wl.q for wl in wls]))
+    qd = cuda(np.concatenate([wl.qdot for wl in wls]))
+    hs = np.linspace(1e-3, 2e-3, len(wls))
+    h = cuda(hs)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        f0, v0 = b.assemble(q, qd, h)  # one workgroup per item
+        b.set_schedule(True, tile_elems)
+        sch = b.schedule()
+        outs = [b.assemble(q, qd, h) for _ in range(3)]  # captured once, replayed
+    stream.synchronize()
+    assert sch["persistent"] == 1 and sch["tile_elems"] == tile_elems
+    assert 1 <= sch["grid_tiles"] and 1 <= sch["grid_ranges"]
+    for f, v in outs:
+        assert rel_err(f.cpu().numpy(), f0.cpu().numpy())[0] <= 1e-13
+        assert rel_err(v.cpu().numpy(), v0.cpu().numpy())[0] <= 1e-13
+    f, vals = outs[-1]
+    for k, wl in enumerate(wls):
+        d0, d1 = b.dof_off[k], b.dof_off[k + 1]
+        z0, z1 = b.nnz_off[k], b.nnz_off[k + 1]
+        om = oracle.Mesh.of(wl.mesh)
+        f_ref, v_ref = oracle.assemble(om, oracle.material_of(wl.material), wl.q, wl.qdot, hs[k], 1.0)
+        assert rel_err(f[d0:d1].cpu().numpy(), f_ref)[0] <= 1e-5, k
+        assert rel_err(vals[z0:z1].cpu().numpy(), v_ref)[0] <= 1e-5, k
+    b.set_schedule(False)
+    assert b.schedule()["persistent"] == 0
+    b.close()
+    for m in meshes:
+        m.close()
+
+
+def test_batch_autotune_caches_its_choice():
+    """The autotuner times every schedule and shape, keeps the fastest, and a
+    batch created later over bodies of the same sizes starts with that choice."""
+    print("[gpu] batch autotune cache", flush=True)
+    wls = batch_workloads(10, 43)
+    q = cuda(np.concatenate([wl.q for wl in wls]))
+    qd = cuda(np.concatenate([wl.qdot for wl in wls]))
+    h = cuda(np.full(len(wls), 1e-3))
+    meshes = [make_mesh(wl, "mixed") for wl in wls]
+    b = TLBatch(meshes)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        shape, ms, f_t, v_t = b.autotune(q, qd, h, reps=2)
+        chosen = b.schedule()
+        f1, v1 = b.assemble(q, qd, h)
+    stream.synchronize()
+    assert ms > 0
+    assert rel_err(f1.cpu().numpy(), f_t.cpu().numpy())[0] <= 1e-13
+    meshes2 = [make_mesh(wl, "mixed") for wl in wls]
+    b2 = TLBatch(meshes2)
+    assert b2.schedule()["persistent"] == chosen["persistent"]
+    assert b2.schedule()["tile_elems"] == chosen["tile_elems"]
+    assert b2.gather_shape()[0] == shape
+    for obj in [b, b2] + meshes + meshes2:
+        obj.close()

@@ -1219,8 +1219,19 @@ __global__ __launch_bounds__(256) void k_force_sum(const int32_t* __restrict__ i
   if (r >= n_rows) return;
   const int64_t I = r / rpn;
   const int j = (int)(r - I * rpn);
+  // four loads in flight, summed in incidence order
   double s = 0.0;
-  for (int32_t x = inc_off[I]; x < inc_off[I + 1]; ++x) s += (double)blocks[(int64_t)x * rpn + j];
+  int32_t x = inc_off[I];
+  const int32_t x1 = inc_off[I + 1];
+  for (; x + 4 <= x1; x += 4) {
+    const R* b = blocks + (int64_t)x * rpn + j;
+    const double v0 = (double)b[0], v1 = (double)b[rpn], v2 = (double)b[2 * rpn], v3 = (double)b[3 * rpn];
+    s += v0;
+    s += v1;
+    s += v2;
+    s += v3;
+  }
+  for (; x < x1; ++x) s += (double)blocks[(int64_t)x * rpn + j];
   f[r] = accum ? f[r] + s : s;
 }
 

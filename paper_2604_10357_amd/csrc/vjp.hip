@@ -13,14 +13,14 @@
 // element by element.  Runs in float64.
 //
 // Shaped like the force-only path: one workgroup holds whole elements, their
-// nodal values (u, qdot, w) go to LDS once, a lane per point runs one
-// reverse-mode stress product (stress_vjp) for both products and the
-// parameter parts, the points'
-// Zhat = dV Z J0^-T stay in LDS, and a lane per (element, coefficient) sums them
-// against the parent gradients into one block per incidence.  The per-node
-// sums then run in a fixed order (the force path's pass 2), and the parameter
-// partials are reduced per workgroup and then in a fixed order: repeated calls
-// give the same bits.
+// nodal values (u, qdot, w) go to LDS once, gathered in one pass, a lane per
+// point runs one reverse-mode stress product (stress_vjp) for the products and
+// the parameter parts, the points' Zhat = dV Z J0^-T stay in LDS, and a lane
+// per (element, coefficient) sums them against the parent gradients into one
+// block per incidence.  The qdot product is formed only when it is asked for.
+// The per-node sums then run in a fixed order (the force path's pass 2), and
+// the parameter partials are reduced per workgroup and then in a fixed order:
+// repeated calls give the same bits.
 #include "kernel_common.h"
 
 namespace tlfea {
@@ -30,12 +30,14 @@ constexpr int kVjpThreads = 256;
 template <class Rule>
 constexpr int vjp_elems() { return kVjpThreads / Rule::NQ; }
 
-template <class Rule>
+// QD: the qdot product is formed too (bqd non-null)
+template <class Rule, bool QD>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_elem(AsmArgs a, const double* __restrict__ w,
                                                          const int32_t* __restrict__ incpos, double* __restrict__ bq,
                                                          double* __restrict__ bqd, double* __restrict__ gpart) {
   constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN, MC = Rule::MC, EB = vjp_elems<Rule>();
-  constexpr size_t NOD = (size_t)EB * NEN * 9 * sizeof(double), ZB = (size_t)EB * NQ * 18 * sizeof(double);
+  constexpr int ZS = QD ? 18 : 9;  // LDS values per point: Zhat of q, then of qdot
+  constexpr size_t NOD = (size_t)EB * NEN * 9 * sizeof(double), ZB = (size_t)EB * NQ * ZS * sizeof(double);
   __shared__ __align__(16) unsigned char smem[NOD > ZB ? NOD : ZB];
   __shared__ double dn[NQ * NEN * 3];  // unit-scaled parent gradients, dN_a(q)_m at 3 (NEN q + a) + m
   __shared__ double red[kVjpThreads / 64][5];
@@ -44,12 +46,25 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_elem(AsmArgs a, const doubl
   const int ne = (int)(a.n_elem - e0 < EB ? a.n_elem - e0 : EB);
   double* nod = reinterpret_cast<double*>(smem);  // 6 per coefficient (u, qdot)
   double* wn = nod + EB * NEN * 6;                // 3 per coefficient (w)
-  gather_nodal<Rule>(a, e0, ne, nod);
+  // u = q - X, qdot and w of every (element, coefficient), all loads of one
+  // coefficient issued together
   for (int idx = tid; idx < ne * NEN; idx += kVjpThreads) {
     const int le = idx / NEN, al = idx - le * NEN;
     const int64_t c = coef_of<Rule>(a.conn + (e0 + le) * NPN, al);
+    double v[12];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) wn[3 * idx + i] = w[3 * c + i];
+    for (int i = 0; i < 3; ++i) {
+      v[i] = a.q[3 * c + i];
+      v[3 + i] = a.X[3 * c + i];
+      v[6 + i] = a.qdot ? a.qdot[3 * c + i] : 0.0;
+      v[9 + i] = w[3 * c + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      nod[6 * idx + i] = v[i] - v[3 + i];
+      nod[6 * idx + 3 + i] = v[6 + i];
+      wn[3 * idx + i] = v[9 + i];
+    }
   }
   for (int idx = tid; idx < NQ * NEN * 3; idx += kVjpThreads) {
     const int q = idx / (3 * NEN), r = idx - 3 * NEN * q;
@@ -100,15 +115,16 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_elem(AsmArgs a, const doubl
   }
 #pragma unroll
   for (int th = 0; th < 5; ++th) part[th] = act ? dV * part[th] : 0.0;
-  double* zr = reinterpret_cast<double*>(smem);  // Zhat of q at 18 p, of qdot at 18 p + 9
+  double* zr = reinterpret_cast<double*>(smem);  // Zhat of q at ZS p, of qdot at ZS p + 9
   if (act) {
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
-        zr[18 * pl + 3 * k + m] = Zq[3 * k] * Jinv[3 * m] + Zq[3 * k + 1] * Jinv[3 * m + 1] + Zq[3 * k + 2] * Jinv[3 * m + 2];
-        zr[18 * pl + 9 + 3 * k + m] =
-            Zd[3 * k] * Jinv[3 * m] + Zd[3 * k + 1] * Jinv[3 * m + 1] + Zd[3 * k + 2] * Jinv[3 * m + 2];
+        zr[ZS * pl + 3 * k + m] = Zq[3 * k] * Jinv[3 * m] + Zq[3 * k + 1] * Jinv[3 * m + 1] + Zq[3 * k + 2] * Jinv[3 * m + 2];
+        if constexpr (QD)
+          zr[ZS * pl + 9 + 3 * k + m] =
+              Zd[3 * k] * Jinv[3 * m] + Zd[3 * k + 1] * Jinv[3 * m + 1] + Zd[3 * k + 2] * Jinv[3 * m + 2];
       }
   }
   // workgroup sums of the five partials, in a fixed order
@@ -130,11 +146,11 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_elem(AsmArgs a, const doubl
     const int le = t / NEN, al = t - le * NEN;
     double g[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     for (int qq = 0; qq < NQ; ++qq) {
-      const double* z = zr + 18 * (le * NQ + qq);
+      const double* z = zr + ZS * (le * NQ + qq);
       const double* d = dn + 3 * (NEN * qq + al);
       const double d0 = d[0], d1 = d[1], d2 = d[2];
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < (QD ? 2 : 1); ++h)
 #pragma unroll
         for (int k = 0; k < 3; ++k) g[h][k] += z[9 * h + 3 * k] * d0 + z[9 * h + 3 * k + 1] * d1 + z[9 * h + 3 * k + 2] * d2;
     }
@@ -145,7 +161,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_elem(AsmArgs a, const doubl
     double* oq = bq + pos * (3 * MC) + 3 * (al % MC);
 #pragma unroll
     for (int k = 0; k < 3; ++k) oq[k] = g[0][k] * s;
-    if (bqd) {
+    if constexpr (QD) {
       double* od = bqd + pos * (3 * MC) + 3 * (al % MC);
 #pragma unroll
       for (int k = 0; k < 3; ++k) od[k] = g[1][k] * s;
@@ -154,22 +170,33 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_elem(AsmArgs a, const doubl
 }
 
 // internal partials (c0, c1, c2, eta, lam_v), summed over the workgroups in a
-// fixed order, -> user parameters
-__global__ __launch_bounds__(256) void k_vjp_finalize(const double* __restrict__ gpart, int64_t n_blocks, int kind,
-                                                      double E, double nu, const double* __restrict__ d_params,
-                                                      double* gparam) {
-  __shared__ double red[256][5];
-  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t b = threadIdx.x; b < n_blocks; b += 256)
-#pragma unroll
-    for (int th = 0; th < 5; ++th) s[th] += gpart[5 * b + th];
-#pragma unroll
-  for (int th = 0; th < 5; ++th) red[threadIdx.x][th] = s[th];
+// fixed order, -> user parameters.  The partials lie flat, five per workgroup;
+// lane t of kFinGroups * 5 sums every kFinGroups * 5-th value from t on (one
+// parameter each, four loads in flight), then a tree over the groups.
+constexpr int kFinGroups = 204, kFinThreads = 1024, kFinTree = 256;
+__global__ __launch_bounds__(kFinThreads) void k_vjp_finalize(const double* __restrict__ gpart, int64_t n_blocks,
+                                                              int kind, double E, double nu,
+                                                              const double* __restrict__ d_params, double* gparam) {
+  constexpr int S = 5 * kFinGroups;
+  __shared__ double red[kFinTree][5];
+  const int t = threadIdx.x;
+  const int64_t n = 5 * n_blocks;
+  double s = 0.0;
+  if (t < S) {
+    int64_t i = t;
+    for (; i + 3 * S < n; i += 4 * S) {
+      const double v0 = gpart[i], v1 = gpart[i + S], v2 = gpart[i + 2 * S], v3 = gpart[i + 3 * S];
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; i < n; i += S) s += gpart[i];
+  }
+  for (int k = t; k < 5 * kFinTree; k += kFinThreads) red[k / 5][k % 5] = k == t ? s : 0.0;  // zero past S
   __syncthreads();
-  for (int half = 128; half > 0; half >>= 1) {
-    if ((int)threadIdx.x < half)
-#pragma unroll
-      for (int th = 0; th < 5; ++th) red[threadIdx.x][th] += red[threadIdx.x + half][th];
+  for (int half = kFinTree / 2; half > 0; half >>= 1) {
+    if (t < 5 * half) red[t / 5][t % 5] += red[t / 5 + half][t % 5];
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
@@ -204,9 +231,14 @@ int launch_vjp_elem(const AsmArgs& a, const double* w, const int32_t* incpos, do
                     double* gpart, hipStream_t s) {
   const int64_t blocks = vjp_blocks<Rule>(a.n_elem);
   if (blocks > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
-  if (blocks > 0)
-    hipLaunchKernelGGL(k_vjp_elem<Rule>, dim3((unsigned)blocks), dim3(kVjpThreads), 0, s, a, w, incpos, bq, bqd,
-                       gpart);
+  if (blocks > 0) {
+    if (bqd)
+      hipLaunchKernelGGL((k_vjp_elem<Rule, true>), dim3((unsigned)blocks), dim3(kVjpThreads), 0, s, a, w, incpos, bq,
+                         bqd, gpart);
+    else
+      hipLaunchKernelGGL((k_vjp_elem<Rule, false>), dim3((unsigned)blocks), dim3(kVjpThreads), 0, s, a, w, incpos,
+                         bq, bqd, gpart);
+  }
   TLFEA_HIP_CHECK(hipGetLastError());
   return TLFEA_OK;
 }
@@ -244,7 +276,7 @@ int launch_vjp(Mesh& m, const double* q, const double* qdot, const double* w, do
   if (gq && (rc = launch_block_sum(m, bq, gq, s))) return rc;
   if (gqdot && (rc = launch_block_sum(m, bqd, gqdot, s))) return rc;
   if (gparam) {
-    hipLaunchKernelGGL(k_vjp_finalize, dim3(1), dim3(256), 0, s, gpart, blocks, m.material, m.params[0],
+    hipLaunchKernelGGL(k_vjp_finalize, dim3(1), dim3(kFinThreads), 0, s, gpart, blocks, m.material, m.params[0],
                        m.params[1], d_params, gparam);
     TLFEA_HIP_CHECK(hipGetLastError());
   }

@@ -116,6 +116,79 @@ __device__ __forceinline__ R record_value(const HatOut<R>& h) {
   }
 }
 
+// Undamped materials: the tangent has major symmetry, Ahat_imkn = Ahat_knim
+// (every term of the factored form is symmetric under (i, m) <-> (k, n) once
+// the viscous parts are zero), so slot (k, i) is slot (i, k) transposed.  An
+// element-row record then holds the six slots with i <= k, in the order (0,0),
+// (0,1), (0,2), (1,1), (1,2), (2,2), each as above (Ahat at 3 m + n, Phat_ik at
+// 9), then Phat_10, Phat_20, Phat_21 and one pad: 64 values instead of 92.
+constexpr int kRecS = 64;
+
+template <int W, typename R>
+__device__ __forceinline__ R record_value_sym(const HatOut<R>& h) {
+  if constexpr (W < 6 * kSlot) {
+    constexpr int sl = W / kSlot, x = W % kSlot;
+    constexpr int i = sl < 3 ? 0 : sl < 5 ? 1 : 2, k = sl < 3 ? sl : sl < 5 ? sl - 2 : 2;
+    if constexpr (x < 9) return hat_entry(h, i, x / 3, k, x % 3);
+    else return h.P[3 * i + k];
+  } else if constexpr (W < 6 * kSlot + 3) {
+    constexpr int j = W - 6 * kSlot, i = j == 0 ? 1 : 2, k = j == 2 ? 1 : 0;
+    return h.P[3 * i + k];
+  } else {
+    return R(0);
+  }
+}
+
+// Where the slot (i, k) of a task lies in an element-row record (full or
+// symmetric layout), and whether its Ahat block is read transposed.
+struct SlotRef {
+  int off;  // first Ahat value
+  int p;    // Phat_ik
+  bool tr;
+};
+template <bool SYM>
+__device__ __forceinline__ SlotRef slot_ref(int i, int k) {
+  if constexpr (!SYM) {
+    return {kSlot * (3 * i + k), kSlot * (3 * i + k) + 9, false};
+  } else {
+    const int lo = i < k ? i : k, hi = i < k ? k : i;
+    const int sl = lo == 0 ? hi : lo == 1 ? hi + 2 : 5;
+    const bool tr = i > k;
+    return {kSlot * sl, tr ? 6 * kSlot + i + k - 1 : kSlot * sl + 9, tr};
+  }
+}
+
+// The ten values of a task's slot at one point of a record in LDS: Ahat_imkn
+// at 3 m + n, then Phat_ik.
+template <bool SYM>
+__device__ __forceinline__ void read_slot(const float* r, const SlotRef& sr, float (&v)[10]) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  if constexpr (!SYM) {
+#pragma unroll
+    for (int x = 0; x < 5; ++x) {
+      const f2 w = *reinterpret_cast<const f2*>(r + sr.off + 2 * x);
+      v[2 * x] = w[0];
+      v[2 * x + 1] = w[1];
+    }
+  } else {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const f2 w = *reinterpret_cast<const f2*>(r + sr.off + 2 * x);
+      v[2 * x] = w[0];
+      v[2 * x + 1] = w[1];
+    }
+    v[8] = r[sr.off + 8];
+    v[9] = r[sr.p];
+    const float a1 = v[1], a2 = v[2], a5 = v[5];
+    v[1] = sr.tr ? v[3] : a1;
+    v[3] = sr.tr ? a1 : v[3];
+    v[2] = sr.tr ? v[6] : a2;
+    v[6] = sr.tr ? a2 : v[6];
+    v[5] = sr.tr ? v[7] : a5;
+    v[7] = sr.tr ? a5 : v[7];
+  }
+}
+
 // Pass 1 with the tangent, one workgroup per 256 consecutive (element, point)
 // indices.  The nodal values of the workgroup's elements (u = q - X and qdot
 // per coefficient) are gathered into LDS once instead of once per point, and
@@ -669,14 +742,15 @@ constexpr int kDnL = 20;          // LDS stride of a node's gradient row (16 use
                                   // of the ten nodes on different banks)
 constexpr int kStgL = 100;        // LDS stride of a staged row block (96 used; spreads the banks)
 
-template <class Rule, int EB = kRowElems>
+template <class Rule, int EB = kRowElems, bool SYM = false>
 __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* __restrict__ incpos,
                                                float* __restrict__ rows, int64_t blk) {
   static_assert(Rule::MC == 1 && Rule::NEN == 10, "element rows are built for T10");
   constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN;
+  constexpr int REC = SYM ? kRecS : kRecL;  // LDS record stride
   static_assert(EB * NQ <= kRowThreads, "a lane per point");
   static_assert(kRowThreads % 64 == 0 && 9 * kRowStage <= 64, "a wave stages whole incidences");
-  __shared__ __align__(16) float rec[EB * NQ * kRecL];
+  __shared__ __align__(16) float rec[EB * NQ * REC];
   __shared__ __align__(16) float dn[NEN * kDnL];  // parent gradients of every node at every point
   __shared__ int32_t pos[EB * NEN];         // incidence position of every (element, node)
   __shared__ __align__(16) float stage_buf[(kRowThreads / 64) * kRowStage * kStgL];  // per-wave row blocks
@@ -703,13 +777,14 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
   HatOut<float> h;
   to_parent<float, true>(o, Jinv, h);
   if (act) {
-    float* r = rec + pl * kRecL;
-    sfor<0, kRecL / 4>([&](auto jc) __attribute__((always_inline)) {
+    float* r = rec + pl * REC;
+    sfor<0, REC / 4>([&](auto jc) __attribute__((always_inline)) {
       constexpr int j = decltype(jc)::value;
       f32x4 v;
       sfor<0, 4>([&](auto xc) __attribute__((always_inline)) {
         constexpr int x = decltype(xc)::value;
-        v[x] = record_value<4 * j + x>(h);
+        if constexpr (SYM) v[x] = record_value_sym<4 * j + x>(h);
+        else v[x] = record_value<4 * j + x>(h);
       });
       *reinterpret_cast<f32x4*>(r + 4 * j) = v;
     });
@@ -745,11 +820,12 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
 #pragma unroll
       for (int b = 0; b < NEN; ++b) acc[hh][b] = 0.0f;
       facc[hh] = 0.0f;
-      const float* base = rec + le * NQ * kRecL + kSlot * sl;
+      const float* base = rec + le * NQ * REC;
+      const SlotRef sr = slot_ref<SYM>(i, k);
       sfor<0, NQ>([&](auto qc) __attribute__((always_inline)) {
         constexpr int qq = decltype(qc)::value;
         Slot<float, true> sv;
-        load_slot<float, true>(base + qq * kRecL, sv);
+        read_slot<SYM>(base + qq * REC, sr, sv.v);
         contract_point<Rule, float, true, true, qq, NEN>(sv, dna[3 * qq], dna[3 * qq + 1], dna[3 * qq + 2], k,
                                                          acc[hh], facc[hh]);
       });
@@ -784,9 +860,9 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
   }
 }
 
-template <class Rule>
+template <class Rule, bool SYM>
 __global__ __launch_bounds__(kRowThreads) void k_elem_rows(AsmArgs a, const int32_t* incpos, float* rows) {
-  elem_rows_tile<Rule>(a, incpos, rows, blockIdx.x);
+  elem_rows_tile<Rule, kRowElems, SYM>(a, incpos, rows, blockIdx.x);
 }
 
 // many bodies: every body starts on a workgroup of its own, found by bisection
@@ -963,13 +1039,14 @@ constexpr int rows_mc_elems() { return kRowsMcThreads / Rule::NQ; }
 template <int NEN>
 constexpr int rows_mc_block() { return 36 * NEN + 36; }
 
-template <class Rule>
+template <class Rule, bool SYM>
 __global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc(AsmArgs a, const int32_t* __restrict__ incpos,
                                                                  float* __restrict__ rows) {
   constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN, EB = rows_mc_elems<Rule>();
   constexpr int BLK = rows_mc_block<NEN>();
+  constexpr int RS = SYM ? kRecS : kRecL;  // LDS record stride (symmetric layout for undamped materials)
   static_assert(Rule::MC == 4 && NEN % 4 == 0 && EB >= 1, "element rows of four-coefficient nodes");
-  constexpr size_t NOD = (size_t)EB * NEN * 6 * sizeof(double), REC = (size_t)EB * NQ * kRecL * sizeof(float);
+  constexpr size_t NOD = (size_t)EB * NEN * 6 * sizeof(double), REC = (size_t)EB * NQ * RS * sizeof(float);
   __shared__ __align__(16) unsigned char smem[NOD > REC ? NOD : REC];
   __shared__ float dn[NQ * NEN * 3];  // unit-scaled parent gradients, dN_a(q)_m at 3 (NEN q + a) + m
   const int tid = threadIdx.x;
@@ -997,13 +1074,14 @@ __global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc(AsmArgs a, cons
   to_parent<float, true>(o, Jinv, h);
   float* rec = reinterpret_cast<float*>(smem);
   if (act) {
-    float* r = rec + pl * kRecL;
-    sfor<0, kRecL / 4>([&](auto jc) __attribute__((always_inline)) {
+    float* r = rec + pl * RS;
+    sfor<0, RS / 4>([&](auto jc) __attribute__((always_inline)) {
       constexpr int j = decltype(jc)::value;
       f32x4 v;
       sfor<0, 4>([&](auto xc) __attribute__((always_inline)) {
         constexpr int x = decltype(xc)::value;
-        v[x] = record_value<4 * j + x>(h);
+        if constexpr (SYM) v[x] = record_value_sym<4 * j + x>(h);
+        else v[x] = record_value<4 * j + x>(h);
       });
       *reinterpret_cast<f32x4*>(r + 4 * j) = v;
     });
@@ -1023,20 +1101,15 @@ __global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc(AsmArgs a, cons
 #pragma unroll
     for (int b = 0; b < NEN; ++b) acc[b] = 0.0f;
     float facc = 0.0f;
-    const float* recp = rec + le * NQ * kRecL + kSlot * s;
+    const float* recp = rec + le * NQ * RS;
+    const SlotRef sr = slot_ref<SYM>(s / 3, k);
     static_assert(NQ % kRowsMcUnroll == 0, "point steps tile the rule");
 #pragma unroll 1
     for (int q0 = 0; q0 < NQ; q0 += kRowsMcUnroll) {
       sfor<0, kRowsMcUnroll>([&](auto uc) __attribute__((always_inline)) {
         const int qq = q0 + decltype(uc)::value;
-        const float* sl = recp + qq * kRecL;
         float v[10];
-#pragma unroll
-        for (int x = 0; x < 5; ++x) {
-          const f32x2 w = *reinterpret_cast<const f32x2*>(sl + 2 * x);
-          v[2 * x] = w[0];
-          v[2 * x + 1] = w[1];
-        }
+        read_slot<SYM>(recp + qq * RS, sr, v);
         const float* d = dn + 3 * (NEN * qq + al);
         const float d0 = d[0], d1 = d[1], d2 = d[2];
         const float t0n = v[0] * d0 + v[3] * d1 + v[6] * d2;
@@ -1404,14 +1477,29 @@ int launch_rows_nodes(const Mesh& m, double* f, double* vals, bool accum, hipStr
   return TLFEA_OK;
 }
 
+// Undamped materials take the symmetric record layout in the element-row
+// pass 1 (TLFEA_SYM_RECORDS=0 keeps the full layout, for comparisons).
+bool sym_records(const Mesh& m) {
+  static const bool on = [] {
+    const char* v = std::getenv("TLFEA_SYM_RECORDS");
+    return !(v && v[0] == '0');
+  }();
+  return on && m.mp.eta == 0.0 && m.mp.lam_v == 0.0;
+}
+
 template <class Rule>
 int launch_rows_mc_points(const Mesh& m, const AsmArgs& a, hipStream_t s) {
   constexpr int EB = rows_mc_elems<Rule>();
   const int64_t blocks = (m.n_elem + EB - 1) / EB;
   if (blocks > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
-  if (blocks > 0)
-    hipLaunchKernelGGL(k_elem_rows_mc<Rule>, dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s, a, m.d_incpos,
-                       (float*)m.d_stage);
+  if (blocks > 0) {
+    if (sym_records(m))
+      hipLaunchKernelGGL((k_elem_rows_mc<Rule, true>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s, a,
+                         m.d_incpos, (float*)m.d_stage);
+    else
+      hipLaunchKernelGGL((k_elem_rows_mc<Rule, false>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s, a,
+                         m.d_incpos, (float*)m.d_stage);
+  }
   TLFEA_HIP_CHECK(hipGetLastError());
   return TLFEA_OK;
 }
@@ -1561,8 +1649,12 @@ int launch_points(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t s) {
     const int64_t blocks = (m.n_elem + kRowElems - 1) / kRowElems;
     if (blocks > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
     if (blocks > 0)
-      hipLaunchKernelGGL(k_elem_rows<RuleT10>, dim3((unsigned)blocks), dim3(kRowThreads), 0, s, a, m.d_incpos,
-                         (float*)m.d_stage);
+      if (sym_records(m))
+        hipLaunchKernelGGL((k_elem_rows<RuleT10, true>), dim3((unsigned)blocks), dim3(kRowThreads), 0, s, a,
+                           m.d_incpos, (float*)m.d_stage);
+      else
+        hipLaunchKernelGGL((k_elem_rows<RuleT10, false>), dim3((unsigned)blocks), dim3(kRowThreads), 0, s, a,
+                           m.d_incpos, (float*)m.d_stage);
     TLFEA_HIP_CHECK(hipGetLastError());
     return TLFEA_OK;
   }

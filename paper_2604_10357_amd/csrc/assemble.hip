@@ -742,6 +742,94 @@ constexpr int kDnL = 20;          // LDS stride of a node's gradient row (16 use
                                   // of the ten nodes on different banks)
 constexpr int kStgL = 100;        // LDS stride of a staged row block (96 used; spreads the banks)
 
+// Phase B of the element rows for a symmetric tangent (undamped materials):
+// K_e^(ki)[b, a] = K_e^(ik)[a, b], so only the slots i <= k are contracted.
+// A wave takes one element at a time, a lane per task (node a, slot i <= k):
+// 60 lanes, each forming the ten entries K_e[3a+i][3b+k] over the points.  The
+// lanes put them into the element's ten row blocks in the wave's LDS buffer,
+// at (a, i, k, b) and, for i < k, transposed at (b, k, i, a); f_a,i is the sum
+// of the parts Phat_ik dN_a,k of the node's lanes, in a fixed order.  Then the
+// wave stores the ten blocks with 16-byte stores of consecutive lanes.  Two
+// thirds of the multiply-adds of the full contraction.
+template <class Rule, int EB>
+__device__ __forceinline__ void elem_rows_sym_contract(const int32_t* __restrict__ incpos, float* __restrict__ rows,
+                                                       int64_t e0, int ne, const float* rec, const float* dn,
+                                                       float* stage_buf) {
+  constexpr int NQ = Rule::NQ, NEN = Rule::NEN;
+  static_assert(6 * NEN <= 64, "a lane per (node, upper slot)");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float* stg = stage_buf + wave * NEN * kStgL;
+  const int tl = lane < 6 * NEN ? lane : 0;  // lanes past the tasks repeat task 0 and store nothing
+  const int an = tl / 6, us = tl - 6 * an;
+  const int i = us < 3 ? 0 : us < 5 ? 1 : 2, k = us < 3 ? us : us < 5 ? us - 2 : 2;
+  const int so = kSlot * us, pt = 6 * kSlot + i + k - 1;  // the slot, Phat_ki (i < k)
+  float dna[16];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const f32x4 x = reinterpret_cast<const f32x4*>(dn + kDnL * an)[u];
+    dna[4 * u] = x[0];
+    dna[4 * u + 1] = x[1];
+    dna[4 * u + 2] = x[2];
+    dna[4 * u + 3] = x[3];
+  }
+  for (int le = wave; le < ne; le += kRowThreads / 64) {  // uniform per wave
+    const int32_t my_pos = lane < NEN ? incpos[(e0 + le) * NEN + lane] : 0;
+    float acc[NEN], fd = 0.0f, ft = 0.0f;
+#pragma unroll
+    for (int b = 0; b < NEN; ++b) acc[b] = 0.0f;
+    const float* base = rec + le * NQ * kRecS;
+    sfor<0, NQ>([&](auto qc) __attribute__((always_inline)) {
+      constexpr int qq = decltype(qc)::value;
+      const float* r = base + qq * kRecS;
+      Slot<float, true> sv;
+#pragma unroll
+      for (int x = 0; x < 5; ++x) {
+        const f32x2 w = *reinterpret_cast<const f32x2*>(r + so + 2 * x);
+        sv.v[2 * x] = w[0];
+        sv.v[2 * x + 1] = w[1];
+      }
+      const float d0 = dna[3 * qq], d1 = dna[3 * qq + 1], d2 = dna[3 * qq + 2];
+      contract_point<Rule, float, true, true, qq, NEN>(sv, d0, d1, d2, k, acc, fd);
+      if (i < k) ft += r[pt] * (i == 0 ? d0 : d1);  // Phat_ki dN_a,i
+    });
+    wave_sync();  // the previous element's blocks have left the buffer
+    if (lane < 6 * NEN) {
+      float* own = stg + an * kStgL + kSlot * (3 * i + k);
+#pragma unroll
+      for (int u = 0; u < NEN / 2; ++u) {
+        f32x2 v;
+        v[0] = acc[2 * u];
+        v[1] = acc[2 * u + 1];
+        *reinterpret_cast<f32x2*>(own + 2 * u) = v;
+      }
+      if (i < k) {
+#pragma unroll
+        for (int b = 0; b < NEN; ++b) stg[b * kStgL + kSlot * (3 * k + i) + an] = acc[b];
+      }
+    }
+    // f_a,0 = (0,0) + (0,1) + (0,2);  f_a,1 = (1,0) + (1,1) + (1,2);  f_a,2 = (2,0) + (2,1) + (2,2),
+    // the (k, i) parts with k > i from the lanes of slot (i, k)
+    const int l0 = 6 * an;
+    const float d01 = __shfl(fd, l0 + 1, 64), d02 = __shfl(fd, l0 + 2, 64), d12 = __shfl(fd, l0 + 4, 64);
+    const float t01 = __shfl(ft, l0 + 1, 64), t02 = __shfl(ft, l0 + 2, 64), t12 = __shfl(ft, l0 + 4, 64);
+    const float d00 = __shfl(fd, l0, 64), d11 = __shfl(fd, l0 + 3, 64), d22 = __shfl(fd, l0 + 5, 64);
+    if (lane < 6 * NEN && us < 3) {
+      const float fv = us == 0 ? (d00 + d01) + d02 : us == 1 ? (t01 + d11) + d12 : (t02 + t12) + d22;
+      stg[an * kStgL + 9 * kSlot + us] = fv;
+      stg[an * kStgL + 9 * kSlot + 3 + us] = 0.0f;
+    }
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < (NEN * kRowBlk / 4 + 63) / 64; ++u) {
+      const int pc = lane + 64 * u, bl = pc / (kRowBlk / 4), pi = pc - bl * (kRowBlk / 4);
+      const int32_t pb = __shfl(my_pos, bl < NEN ? bl : 0, 64);
+      if (bl < NEN)
+        *reinterpret_cast<f32x4*>(rows + (int64_t)pb * kRowBlk + 4 * pi) =
+            *reinterpret_cast<const f32x4*>(stg + bl * kStgL + 4 * pi);
+    }
+  }
+}
+
 template <class Rule, int EB = kRowElems, bool SYM = false>
 __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* __restrict__ incpos,
                                                float* __restrict__ rows, int64_t blk) {
@@ -752,8 +840,8 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
   static_assert(kRowThreads % 64 == 0 && 9 * kRowStage <= 64, "a wave stages whole incidences");
   __shared__ __align__(16) float rec[EB * NQ * REC];
   __shared__ __align__(16) float dn[NEN * kDnL];  // parent gradients of every node at every point
-  __shared__ int32_t pos[EB * NEN];         // incidence position of every (element, node)
-  __shared__ __align__(16) float stage_buf[(kRowThreads / 64) * kRowStage * kStgL];  // per-wave row blocks
+  __shared__ int32_t pos[SYM ? 1 : EB * NEN];     // incidence position of every (element, node)
+  __shared__ __align__(16) float stage_buf[(kRowThreads / 64) * (SYM ? NEN : kRowStage) * kStgL];  // per-wave blocks
   static_assert(EB * NEN * 6 * sizeof(double) <= sizeof(rec), "nodal values fit the record area");
   const int tid = threadIdx.x;
   const int64_t e0 = blk * EB;
@@ -761,7 +849,8 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
   // 1. nodal values, the tables of the tasks, then each point's kinematics
   double* nod = reinterpret_cast<double*>(rec);
   gather_nodal<Rule>(a, e0, ne, nod);
-  for (int idx = tid; idx < ne * NEN; idx += kRowThreads) pos[idx] = incpos[e0 * NPN + idx];
+  if constexpr (!SYM)
+    for (int idx = tid; idx < ne * NEN; idx += kRowThreads) pos[idx] = incpos[e0 * NPN + idx];
   for (int idx = tid; idx < NEN * 16; idx += kRowThreads) dn[kDnL * (idx / 16) + idx % 16] = Rule::template rows<float>(idx / 16)[idx % 16];
   __syncthreads();
   const bool act = tid < ne * NQ;
@@ -790,6 +879,9 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
     });
   }
   __syncthreads();
+  if constexpr (SYM) {
+    elem_rows_sym_contract<Rule, EB>(incpos, rows, e0, ne, rec, dn, stage_buf);
+  } else {
   // 3. a lane per task: each wave takes 2 x 7 whole incidences at a time (63
   //    lanes, two tasks of the same slot each), contracts the element's
   //    points, and stages the row blocks, 7 at a time, in its LDS buffer; f_a,i
@@ -857,6 +949,7 @@ __device__ __forceinline__ void elem_rows_tile(const AsmArgs& a, const int32_t* 
               *reinterpret_cast<const f32x4*>(stg + bl * kStgL + 4 * pi);
       }
     });
+  }
   }
 }
 
@@ -1039,6 +1132,87 @@ constexpr int rows_mc_elems() { return kRowsMcThreads / Rule::NQ; }
 template <int NEN>
 constexpr int rows_mc_block() { return 36 * NEN + 36; }
 
+// Phase B of the ANCF element rows for a symmetric tangent (undamped
+// materials): only the slots i <= k are contracted, a lane per task (element,
+// slot, coefficient a), coefficients fastest.  A task writes its NEN entries
+// K_e[(a, i), (b, k)] as in the full form and, for i < k, the same values as
+// the entries K_e[(b, k), (a, i)] of the blocks of the column coefficients'
+// nodes (the lanes of consecutive a write consecutive values), plus the force
+// parts of rows i and, for i < k, k.  Two thirds of the full form's tasks.
+template <class Rule, int EB>
+__device__ __forceinline__ void rows_mc_sym_contract(const AsmArgs& a, const int32_t* __restrict__ incpos,
+                                                     float* __restrict__ rows, int64_t e0, int ne, const float* rec,
+                                                     const float* dn) {
+  constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN;
+  constexpr int BLK = rows_mc_block<NEN>();
+  const int tid = threadIdx.x;
+  const int ntask = ne * NEN * 6;
+  for (int t0 = 0; t0 < EB * NEN * 6; t0 += kRowsMcThreads) {
+    const int t = t0 + tid;
+    const bool on = t < ntask;
+    const int tt = on ? t : ntask - 1;
+    const int le = tt / (NEN * 6), r6 = tt - le * NEN * 6, us = r6 / NEN, al = r6 - us * NEN;
+    const int i = us < 3 ? 0 : us < 5 ? 1 : 2, k = us < 3 ? us : us < 5 ? us - 2 : 2;
+    const int so = kSlot * us, pt = 6 * kSlot + i + k - 1;  // the slot, Phat_ki (i < k)
+    float acc[NEN];
+#pragma unroll
+    for (int b = 0; b < NEN; ++b) acc[b] = 0.0f;
+    float facc = 0.0f, ft = 0.0f;
+    const float* recp = rec + le * NQ * kRecS;
+    static_assert(NQ % kRowsMcUnroll == 0, "point steps tile the rule");
+#pragma unroll 1
+    for (int q0 = 0; q0 < NQ; q0 += kRowsMcUnroll) {
+      sfor<0, kRowsMcUnroll>([&](auto uc) __attribute__((always_inline)) {
+        const int qq = q0 + decltype(uc)::value;
+        const float* r = recp + qq * kRecS;
+        float v[10];
+#pragma unroll
+        for (int x = 0; x < 5; ++x) {
+          const f32x2 w = *reinterpret_cast<const f32x2*>(r + so + 2 * x);
+          v[2 * x] = w[0];
+          v[2 * x + 1] = w[1];
+        }
+        const float* d = dn + 3 * (NEN * qq + al);
+        const float d0 = d[0], d1 = d[1], d2 = d[2];
+        const float t0n = v[0] * d0 + v[3] * d1 + v[6] * d2;
+        const float t1n = v[1] * d0 + v[4] * d1 + v[7] * d2;
+        const float t2n = v[2] * d0 + v[5] * d1 + v[8] * d2;
+        facc += v[9] * (k == 0 ? d0 : k == 1 ? d1 : d2);
+        if (i < k) ft += r[pt] * (i == 0 ? d0 : d1);
+#pragma unroll
+        for (int b = 0; b < NEN; ++b)
+          acc[b] += t0n * Rule::dNf_rt(qq, b, 0) + t1n * Rule::dNf_rt(qq, b, 1) + t2n * Rule::dNf_rt(qq, b, 2);
+      });
+    }
+    if (on) {
+      double sc[4];
+      element_scales<Rule>(a, e0 + le, sc);
+      const float s_a = (float)sc[al & 3];
+      const int32_t* ip = incpos + (e0 + le) * NPN;
+      const int c = al & 3, r = 3 * c + i;  // block row (kind, i)
+      float* blk = rows + (int64_t)ip[al >> 2] * BLK;
+      f32x4* outv = reinterpret_cast<f32x4*>(blk + (3 * r + k) * NEN);
+#pragma unroll
+      for (int u = 0; u < NEN / 4; ++u) {
+        f32x4 w;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) w[x] = acc[4 * u + x] * s_a * (float)sc[x];  // b = 4 u + x: kind x
+        outv[u] = w;
+      }
+      blk[36 * NEN + 3 * r + k] = facc * s_a;
+      if (i < k) {
+        blk[36 * NEN + 3 * (3 * c + k) + i] = ft * s_a;
+#pragma unroll
+        for (int nb = 0; nb < NPN; ++nb) {
+          float* ob = rows + (int64_t)ip[nb] * BLK;
+#pragma unroll
+          for (int x = 0; x < 4; ++x) ob[(3 * (3 * x + k) + i) * NEN + al] = acc[4 * nb + x] * s_a * (float)sc[x];
+        }
+      }
+    }
+  }
+}
+
 template <class Rule, bool SYM>
 __global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc(AsmArgs a, const int32_t* __restrict__ incpos,
                                                                  float* __restrict__ rows) {
@@ -1087,6 +1261,10 @@ __global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc(AsmArgs a, cons
     });
   }
   __syncthreads();
+  if constexpr (SYM) {
+    rows_mc_sym_contract<Rule, EB>(a, incpos, rows, e0, ne, rec, dn);
+    return;
+  }
   // 2. a lane per task (element, coefficient a, row i, component k), tasks in
   //    block order; the point loop is uniform across the workgroup, so the
   //    gradients dN_b(q) of the columns come through the scalar cache

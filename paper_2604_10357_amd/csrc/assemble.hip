@@ -1213,7 +1213,107 @@ __device__ __forceinline__ void rows_mc_sym_contract(const AsmArgs& a, const int
   }
 }
 
-template <class Rule, bool SYM>
+// Phase B of the shell's element rows on the matrix cores.  With
+// D[(q,m), a] = dN_a,m(q) (the parent gradients, the same for every element)
+// and T[(q,m), b] = sum_n Ahat_q,imkn dN_b,n(q), the slot (i, k) of K_e is the
+// 16 x 16 product K^(ik) = D^T T over the 3 NQ values of (q, m): one MFMA tile,
+// no padding in a or b (sixteen coefficients), the (q, m) axis padded to a
+// multiple of four.  A wave takes one element at a time and runs the 16x16x4
+// FP32 MFMA over the (q, m) axis in steps of four, for all the element's slots
+// at once (independent accumulators, so the matrix-core chain of one slot
+// overlaps the others); in each step lane l feeds D[(q,m), l % 16] and forms
+// T[(q,m), l % 16] of every slot (three multiply-adds each from the LDS
+// record), (q, m) = 4 step + l / 16.  Lane l then holds K^(ik)[4 (l / 16) +
+// r][l % 16], r < 4, and stores them with the scales into the block of node
+// l / 16 (rows of kind r); for a symmetric tangent (SYM: the six slots i <= k)
+// a lane of a slot with i < k also stores its four values, consecutive in a,
+// as K_e[(b, k), (a, i)] into the block of the column's node.  The force parts
+// are spread over the four lane groups (a quarter of the points each) and
+// summed in a fixed order.
+template <bool SYM, int S>
+struct McSlot {
+  static constexpr int i = SYM ? (S < 3 ? 0 : S < 5 ? 1 : 2) : S / 3;
+  static constexpr int k = SYM ? (S < 3 ? S : S < 5 ? S - 2 : 2) : S % 3;
+  static constexpr int off = SYM ? kSlot * S : kSlot * (3 * i + k);
+};
+
+template <class Rule, int EB, bool SYM>
+__device__ __forceinline__ void rows_mc_mfma_contract(const AsmArgs& a, const int32_t* __restrict__ incpos,
+                                                      float* __restrict__ rows, int64_t e0, int ne, const float* rec,
+                                                      const float* dn) {
+  constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN, BLK = rows_mc_block<NEN>();
+  static_assert(NEN == 16, "one 16 x 16 tile per slot");
+  constexpr int RS = SYM ? kRecS : kRecL;
+  constexpr int KK = 3 * NQ, NSTEP = (KK + 3) / 4, NSL = SYM ? 6 : 9, NW = kRowsMcThreads / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  for (int le = wave; le < ne; le += NW) {  // uniform per wave
+    const float* re = rec + le * NQ * RS;
+    f32x4 acc[NSL];
+#pragma unroll
+    for (int t = 0; t < NSL; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 2
+    for (int st = 0; st < NSTEP; ++st) {
+      const int kk = 4 * st + g;
+      const bool live = kk < KK;
+      const int q = live ? kk / 3 : 0, m = kk - 3 * q;
+      const float* d = dn + 3 * (NEN * q + c16);  // dN_c16(q)
+      const float d0 = d[0], d1 = d[1], d2 = d[2];
+      const float av = live ? (m == 0 ? d0 : m == 1 ? d1 : d2) : 0.0f;
+      const float* r = re + q * RS + 3 * (live ? m : 0);
+      sfor<0, NSL>([&](auto sc_) __attribute__((always_inline)) {
+        constexpr int S = decltype(sc_)::value;
+        constexpr int off = McSlot<SYM, S>::off;
+        const float bv = r[off] * d0 + r[off + 1] * d1 + r[off + 2] * d2;
+        acc[S] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[S], 0, 0, 0);
+      });
+    }
+    // force parts of node c16: Phat_ik dN_c16,k (and Phat_ki dN_c16,i for i < k), a quarter of the points per group
+    float fd[NSL], ft[3];
+#pragma unroll
+    for (int t = 0; t < NSL; ++t) fd[t] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) ft[t] = 0.0f;
+    for (int q = g; q < NQ; q += 4) {
+      const float* d = dn + 3 * (NEN * q + c16);
+      const float* r = re + q * RS;
+      sfor<0, NSL>([&](auto sc_) __attribute__((always_inline)) {
+        constexpr int S = decltype(sc_)::value, i = McSlot<SYM, S>::i, k = McSlot<SYM, S>::k;
+        fd[S] += r[McSlot<SYM, S>::off + 9] * d[k];
+        if constexpr (SYM && i < k) ft[i + k - 1] += r[6 * kSlot + i + k - 1] * d[i];
+      });
+    }
+#pragma unroll
+    for (int t = 0; t < NSL; ++t)
+      fd[t] = ((fd[t] + __shfl_down(fd[t], 16, 64)) + __shfl_down(fd[t], 32, 64)) + __shfl_down(fd[t], 48, 64);
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      ft[t] = ((ft[t] + __shfl_down(ft[t], 16, 64)) + __shfl_down(ft[t], 32, 64)) + __shfl_down(ft[t], 48, 64);
+    double sc[4];
+    element_scales<Rule>(a, e0 + le, sc);
+    const int32_t* ip = incpos + (e0 + le) * NPN;
+    const float sb = (float)sc[c16 & 3], sa = sb;  // column scale of b = c16; row scale of a = c16 (forces)
+    float* blk = rows + (int64_t)ip[g] * BLK;      // node of the rows a = 4 g + r
+    float* cb = rows + (int64_t)ip[c16 >> 2] * BLK;  // node of coefficient c16
+    sfor<0, NSL>([&](auto sc_) __attribute__((always_inline)) {
+      constexpr int S = decltype(sc_)::value, i = McSlot<SYM, S>::i, k = McSlot<SYM, S>::k;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) blk[(3 * (3 * r + i) + k) * NEN + c16] = acc[S][r] * (float)sc[r] * sb;
+      if (g == 0) {
+        cb[36 * NEN + 3 * (3 * (c16 & 3) + i) + k] = fd[S] * sa;
+        if constexpr (SYM && i < k) cb[36 * NEN + 3 * (3 * (c16 & 3) + k) + i] = ft[i + k - 1] * sa;
+      }
+      if constexpr (SYM && i < k) {
+        f32x4 w;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w[r] = acc[S][r] * (float)sc[r] * sb;
+        *reinterpret_cast<f32x4*>(cb + (3 * (3 * (c16 & 3) + k) + i) * NEN + 4 * g) = w;
+      }
+    });
+  }
+}
+
+template <class Rule, bool SYM, bool MF>
 __global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc(AsmArgs a, const int32_t* __restrict__ incpos,
                                                                  float* __restrict__ rows) {
   constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN, EB = rows_mc_elems<Rule>();
@@ -1261,6 +1361,10 @@ __global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc(AsmArgs a, cons
     });
   }
   __syncthreads();
+  if constexpr (MF) {
+    rows_mc_mfma_contract<Rule, EB, SYM>(a, incpos, rows, e0, ne, rec, dn);
+    return;
+  }
   if constexpr (SYM) {
     rows_mc_sym_contract<Rule, EB>(a, incpos, rows, e0, ne, rec, dn);
     return;
@@ -1665,18 +1769,35 @@ bool sym_records(const Mesh& m) {
   return on && m.mp.eta == 0.0 && m.mp.lam_v == 0.0;
 }
 
+// The shell's element-row contraction on the matrix cores (TLFEA_MC_MFMA=0
+// keeps the vector form, for comparisons).
+bool mc_mfma() {
+  static const bool on = [] {
+    const char* v = std::getenv("TLFEA_MC_MFMA");
+    return !(v && v[0] == '0');
+  }();
+  return on;
+}
+
 template <class Rule>
 int launch_rows_mc_points(const Mesh& m, const AsmArgs& a, hipStream_t s) {
   constexpr int EB = rows_mc_elems<Rule>();
   const int64_t blocks = (m.n_elem + EB - 1) / EB;
   if (blocks > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
+  constexpr bool MF = Rule::NEN == 16;  // the shell's 16 x 16 slot tiles go to the matrix cores
   if (blocks > 0) {
-    if (sym_records(m))
-      hipLaunchKernelGGL((k_elem_rows_mc<Rule, true>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s, a,
+    if (sym_records(m) && mc_mfma())
+      hipLaunchKernelGGL((k_elem_rows_mc<Rule, true, MF>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s, a,
+                         m.d_incpos, (float*)m.d_stage);
+    else if (sym_records(m))
+      hipLaunchKernelGGL((k_elem_rows_mc<Rule, true, false>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s,
+                         a, m.d_incpos, (float*)m.d_stage);
+    else if (mc_mfma())
+      hipLaunchKernelGGL((k_elem_rows_mc<Rule, false, MF>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s, a,
                          m.d_incpos, (float*)m.d_stage);
     else
-      hipLaunchKernelGGL((k_elem_rows_mc<Rule, false>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s, a,
-                         m.d_incpos, (float*)m.d_stage);
+      hipLaunchKernelGGL((k_elem_rows_mc<Rule, false, false>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s,
+                         a, m.d_incpos, (float*)m.d_stage);
   }
   TLFEA_HIP_CHECK(hipGetLastError());
   return TLFEA_OK;

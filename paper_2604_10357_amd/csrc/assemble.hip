@@ -1784,17 +1784,19 @@ int launch_rows_mc_points(const Mesh& m, const AsmArgs& a, hipStream_t s) {
   constexpr int EB = rows_mc_elems<Rule>();
   const int64_t blocks = (m.n_elem + EB - 1) / EB;
   if (blocks > INT32_MAX) return TLFEA_ERR_TOO_LARGE;
-  constexpr bool MF = Rule::NEN == 16;  // the shell's 16 x 16 slot tiles go to the matrix cores
+  // the shell's 16 x 16 slot tiles on the matrix cores (the beam's 8 x 8 slots
+  // would fill half a tile: slower than its vector form, measured)
+  constexpr bool MF = Rule::NEN == 16;
   if (blocks > 0) {
     if (sym_records(m) && mc_mfma())
-      hipLaunchKernelGGL((k_elem_rows_mc<Rule, true, MF>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s, a,
-                         m.d_incpos, (float*)m.d_stage);
+      hipLaunchKernelGGL((k_elem_rows_mc<Rule, true, MF>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s,
+                         a, m.d_incpos, (float*)m.d_stage);
     else if (sym_records(m))
       hipLaunchKernelGGL((k_elem_rows_mc<Rule, true, false>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s,
                          a, m.d_incpos, (float*)m.d_stage);
     else if (mc_mfma())
-      hipLaunchKernelGGL((k_elem_rows_mc<Rule, false, MF>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s, a,
-                         m.d_incpos, (float*)m.d_stage);
+      hipLaunchKernelGGL((k_elem_rows_mc<Rule, false, MF>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s,
+                         a, m.d_incpos, (float*)m.d_stage);
     else
       hipLaunchKernelGGL((k_elem_rows_mc<Rule, false, false>), dim3((unsigned)blocks), dim3(kRowsMcThreads), 0, s,
                          a, m.d_incpos, (float*)m.d_stage);

@@ -45,9 +45,9 @@ def contraction_flop(wl):
 # committed counter reports: file and the two kernels of the mixed call, per workload
 TRAFFIC = {
     "t10_beam": ("hbm_traffic_t10_beam_200x20x20_mixed.json",
-                 ("k_elem_rows<RuleT10>", "k_gather_rows<true, true, false>")),
+                 ("k_elem_rows<RuleT10, false>", "k_gather_rows<true, true, false>")),
     "ancf_beam": ("hbm_traffic_ancf3243_chain_500000_mixed.json",
-                  ("k_elem_rows_mc<RuleBeam>", "k_gather_rows_mc<RuleBeam, true, true, false>")),
+                  ("k_elem_rows_mc<RuleBeam, true, false>", "k_gather_rows_mc<RuleBeam, true, true, false>")),
 }
 
 

@@ -195,6 +195,14 @@ int tlfea_internal_force(tlfea_mesh_t mesh, const double* d_q, const double* d_q
 int tlfea_internal_force_noalloc(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double* d_f,
                                  void* stream);
 
+/* Kernel forms of the tangent calls below (results equal up to rounding
+ * order; Sec. 4.4.2, Eq. tangent_block): in mixed precision, a material
+ * without Kelvin-Voigt damping has a symmetric tangent, and the element pass
+ * then contracts only the slots i <= k of every point's tangent and stores the
+ * others by transposition; the shell's contraction runs on the matrix cores.
+ * Environment TLFEA_SYM_RECORDS=0 and TLFEA_MC_MFMA=0 (read once per process)
+ * keep the full contraction and the vector form, for comparisons. */
+
 /* CSR values of h * df/dq + df/dqdot = d f_int(q_n + h v, v) / dv -> d_vals (nnz). */
 int tlfea_tangent(tlfea_mesh_t mesh, const double* d_q, const double* d_qdot, double h,
                   double* d_vals, void* stream);

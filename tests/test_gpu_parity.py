@@ -30,6 +30,11 @@ def small_cases():
     sh.material = W.Material(W.SVK, (2e9, 0.3, 0.0), 5e3, 5e3)
     sh.qdot = np.random.default_rng(16).normal(0, 0.05, sh.q.shape)
     out.append(("ancf_3x3_443_kv", sh))
+    # the 3x3x2 shell with damping: the full tangent layout on the matrix cores
+    sd = W.shell_plate(4, 17, "ancf_4x3_332_kv", thickness=0.02)
+    sd.material = W.Material(W.SVK, (2e9, 0.3, 0.0), 5e3, 5e3)
+    sd.qdot = np.random.default_rng(18).normal(0, 0.05, sd.q.shape)
+    out.append(("ancf_4x3_332_kv", sd))
     return out
 
 

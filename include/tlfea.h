@@ -440,7 +440,7 @@ int tlfea_batch_assemble_loop(tlfea_batch_t batch, const double* d_q, const doub
                               const double* d_h, double* d_f, double* d_vals, void* stream);
 
 /* Schedule of the batched element-row launches (T10 bodies in mixed
- * precision; the benchmark spec's persistent batched form).  persistent = 0: one
+ * precision; the persistent batched form).  persistent = 0: one
  * workgroup per element tile and per node range (the default).  persistent =
  * 1: grids of as many workgroups as the GPU holds at once, which take work
  * items from device counters: tiles of tile_elems (25 or 16) elements, full

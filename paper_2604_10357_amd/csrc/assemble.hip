@@ -205,9 +205,10 @@ constexpr size_t stage_lds_bytes() {
   return nodal > trans ? nodal : trans;
 }
 
-template <class Rule, typename R>
+template <class Rule, typename R, bool SYM = false>
 __device__ __forceinline__ void stage_tile(const AsmArgs& a, R* stage, int64_t blk) {
   constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN;
+  constexpr int REC = SYM ? kRecS : kRecK;  // record length (symmetric layout for undamped materials)
   constexpr int EB = stage_elems<Rule>();
   using V = typename Vec4<R>::type;
   constexpr int PER = (int)(sizeof(V) / sizeof(R));
@@ -240,7 +241,8 @@ __device__ __forceinline__ void stage_tile(const AsmArgs& a, R* stage, int64_t b
   constexpr int LS = CW + 16 / (int)sizeof(R);   // lane stride in the buffer (padded)
   R* tb = reinterpret_cast<R*>(smem) + wave * 64 * LS;
   const int64_t pw = p0 + 64 * wave;
-  sfor<0, kRecK / CW>([&](auto cc) __attribute__((always_inline)) {
+  static_assert(REC % CW == 0, "records of whole 128-byte pieces");
+  sfor<0, REC / CW>([&](auto cc) __attribute__((always_inline)) {
     constexpr int ch = decltype(cc)::value;
     wave_sync();
     sfor<0, CW / PER>([&](auto jc) __attribute__((always_inline)) {
@@ -248,7 +250,8 @@ __device__ __forceinline__ void stage_tile(const AsmArgs& a, R* stage, int64_t b
       V v;
       sfor<0, PER>([&](auto xc) __attribute__((always_inline)) {
         constexpr int x = decltype(xc)::value;
-        v[x] = record_value<ch * CW + j * PER + x>(h);
+        if constexpr (SYM) v[x] = record_value_sym<ch * CW + j * PER + x>(h);
+        else v[x] = record_value<ch * CW + j * PER + x>(h);
       });
       *reinterpret_cast<V*>(tb + lane * LS + j * PER) = v;
     });
@@ -257,15 +260,15 @@ __device__ __forceinline__ void stage_tile(const AsmArgs& a, R* stage, int64_t b
     for (int s8 = 0; s8 < 8; ++s8) {
       const int r = 8 * s8 + (lane >> 3), j = lane & 7;
       if (pw + r < npts)
-        *reinterpret_cast<V*>(stage + (pw + r) * kRecK + ch * CW + j * PER) =
+        *reinterpret_cast<V*>(stage + (pw + r) * REC + ch * CW + j * PER) =
             *reinterpret_cast<const V*>(tb + r * LS + j * PER);
     }
   });
 }
 
-template <class Rule, typename R>
+template <class Rule, typename R, bool SYM>
 __global__ __launch_bounds__(kStageThreads) void k_stage_tile(AsmArgs a, R* stage) {
-  stage_tile<Rule, R>(a, stage, blockIdx.x);
+  stage_tile<Rule, R, SYM>(a, stage, blockIdx.x);
 }
 
 // many bodies: every body starts on a block of its own, found by bisection
@@ -368,11 +371,11 @@ constexpr int staged_points() {
   return direct_slots<Rule, R, WANT_K>() ? (kStagedPoints < Rule::NQ ? kStagedPoints : Rule::NQ) : Rule::NQ;
 }
 
-template <class Rule, typename R, bool WANT_K>
+template <class Rule, typename R, bool WANT_K, bool SYM = false>
 constexpr size_t wave_buf_bytes() {
   return staged_points<Rule, R, WANT_K>() == 0
              ? 0
-             : (size_t)chunk_incidences(9 * Rule::MC) * (WANT_K ? kRecK : kRecF) * sizeof(R);
+             : (size_t)chunk_incidences(9 * Rule::MC) * (WANT_K ? (SYM ? kRecS : kRecK) : kRecF) * sizeof(R);
 }
 
 // The same with a run-time point index q (long rules); q is uniform across the
@@ -455,16 +458,35 @@ __device__ __forceinline__ void add_mass_term(const GatherArgs& g, int32_t I0, i
   }
 }
 
+// A slot read from a symmetric record: the lower slots (i > k) are the upper
+// ones transposed, and Phat_ik of a lower slot lies after the six slots.
+template <bool SYM, typename R, bool KREC>
+__device__ __forceinline__ void sym_slot_fix(Slot<R, KREC>& sl, const R* recb, const SlotRef& sr) {
+  if constexpr (SYM) {
+    const R a1 = sl.v[1], a2 = sl.v[2], a5 = sl.v[5];
+    sl.v[1] = sr.tr ? sl.v[3] : a1;
+    sl.v[3] = sr.tr ? a1 : sl.v[3];
+    sl.v[2] = sr.tr ? sl.v[6] : a2;
+    sl.v[6] = sr.tr ? a2 : sl.v[6];
+    sl.v[5] = sr.tr ? sl.v[7] : a5;
+    sl.v[7] = sr.tr ? a5 : sl.v[7];
+    sl.v[9] = recb[sr.p];
+  }
+}
+
 // KREC: the records carry the tangent layout (a pass 1 with the tangent); the
 // force alone can also be taken from them (WANT_K false).
-template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM, bool KREC = WANT_K>
+// SYM: symmetric tangent records (float64 only; the lane's slot may be read
+// transposed).
+template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM, bool KREC = WANT_K, bool SYM = false>
 __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, int32_t I1, unsigned char* smem,
                                              int32_t* pre, int32_t* rowo) {
   static_assert(KREC || !WANT_K, "the tangent needs tangent records");
+  static_assert(!SYM || (KREC && sizeof(R) == 8), "symmetric records: float64 tangent records");
   constexpr int NQ = Rule::NQ, NPN = Rule::NPN, MC = Rule::MC, NEN = Rule::NEN;
   constexpr int RPN = 3 * MC;  // CSR rows per node
   constexpr int TPI = 3 * RPN; // tasks per incidence: (coefficient kind, row, component)
-  constexpr int REC = KREC ? kRecK : kRecF;
+  constexpr int REC = KREC ? (SYM ? kRecS : kRecK) : kRecF;
   constexpr int NI = chunk_incidences(TPI);
   using V = typename Vec4<R>::type;
   constexpr int PER = (int)(sizeof(V) / sizeof(R));
@@ -484,7 +506,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   // LDS: incidence -> node table, wave record buffers, CSR segment + forces
   uint8_t* incn = smem;
   R* wbuf = reinterpret_cast<R*>(smem + g.inc_cap) + wave * NI * REC;
-  double* lds = reinterpret_cast<double*>(smem + g.inc_cap + nwave * wave_buf_bytes<Rule, R, KREC>());
+  double* lds = reinterpret_cast<double*>(smem + g.inc_cap + nwave * wave_buf_bytes<Rule, R, KREC, SYM>());
   const int nn = I1 - I0;
   const int64_t row0 = (int64_t)RPN * I0, row1 = (int64_t)RPN * I1;
   const int64_t seg0 = WANT_K ? g.row_off[row0] : 0, seg1 = WANT_K ? g.row_off[row1] : 0;
@@ -568,7 +590,9 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
     const int64_t e = packed >> 4;
     const int a = packed & 15;
     const int al = MC * a + ca;
-    const R* mine = wbuf + (t / TPI - j0) * REC + (KREC ? kSlot * (3 * i + k) : 4 * i + k);
+    const SlotRef sr = slot_ref<SYM>(i, k);
+    const R* recb = wbuf + (t / TPI - j0) * REC;  // the lane's record in the wave buffer
+    const R* mine = recb + (KREC ? sr.off : 4 * i + k);
     // slot-map row of (e, a): one aligned vector load
     constexpr int RST = rank_stride(NPN);
     uint32_t rkw[RST / 4];
@@ -641,6 +665,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
               buf[q % PDS][kk] = stagev[src[kk] + (q + PDS) * VPP];
           }
           load_slot<R, KREC>(mine, sl);
+          sym_slot_fix<SYM>(sl, recb, sr);
         }
         contract_point<Rule, R, WANT_F, WANT_K, q, NB, KREC>(sl, dna[3 * q], dna[3 * q + 1], dna[3 * q + 2], k, acc,
                                                              facc);
@@ -662,6 +687,7 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
           }
           Slot<R, KREC> sl;
           load_slot<R, KREC>(mine, sl);
+          sym_slot_fix<SYM>(sl, recb, sr);
           contract_point_rt<Rule, R, WANT_F, WANT_K, NB, KREC>(sl, q, al, k, sc_al, acc, facc);
         });
       }
@@ -688,13 +714,13 @@ __device__ __forceinline__ void gather_range(const GatherArgs& g, int32_t I0, in
   }
 }
 
-template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM, bool KREC>
+template <class Rule, typename R, bool WANT_F, bool WANT_K, bool ACCUM, bool KREC, bool SYM>
 __global__ __launch_bounds__(512) void k_gather(GatherArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t pre[kMaxRangeNodes + 1];
   __shared__ int32_t rowo[kMaxRangeNodes * 3 * Rule::MC];
   const int r = remap_tile(blockIdx.x, gridDim.x);
-  gather_range<Rule, R, WANT_F, WANT_K, ACCUM, KREC>(g, g.ranges[r], g.ranges[r + 1], smem, pre, rowo);
+  gather_range<Rule, R, WANT_F, WANT_K, ACCUM, KREC, SYM>(g, g.ranges[r], g.ranges[r + 1], smem, pre, rowo);
 }
 
 template <class Rule, typename R>
@@ -1657,9 +1683,12 @@ int launch_points_rule(const Mesh& m, const AsmArgs& a, bool want_k, hipStream_t
   if (npts > (int64_t)INT32_MAX * 256) return TLFEA_ERR_TOO_LARGE;
   if (npts == 0) return TLFEA_OK;
   R* stage = (R*)m.d_stage;
-  if (want_k)
-    hipLaunchKernelGGL((k_stage_tile<Rule, R>), dim3(grid_of(npts, kStageThreads)), dim3(kStageThreads), 0, s, a,
-                       stage);
+  if (want_k && point_records_sym(m, true))
+    hipLaunchKernelGGL((k_stage_tile<Rule, R, sizeof(R) == 8>), dim3(grid_of(npts, kStageThreads)),
+                       dim3(kStageThreads), 0, s, a, stage);
+  else if (want_k)
+    hipLaunchKernelGGL((k_stage_tile<Rule, R, false>), dim3(grid_of(npts, kStageThreads)), dim3(kStageThreads), 0,
+                       s, a, stage);
   else
     hipLaunchKernelGGL((k_stage<Rule, R, false>), dim3(grid_of(npts, 256)), dim3(256), 0, s, a, stage);
   TLFEA_HIP_CHECK(hipGetLastError());
@@ -1682,6 +1711,7 @@ int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals,
   const bool want_f = f != nullptr, want_k = vals != nullptr;
   if (want_k && !tangent_records) return TLFEA_ERR_INVALID;
   const bool krec = tangent_records;
+  const bool sym = krec && m.staged_sym;  // symmetric float64 records from pass 1
   if (!records_addressable<Rule, R>(m.n_elem, want_k)) return TLFEA_ERR_TOO_LARGE;
   GatherArgs g{};
   g.ranges = m.d_ranges;
@@ -1700,13 +1730,19 @@ int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals,
   g.row_off_u = mt.row_off_u;
   g.inc_cap = (int)((m.max_range_inc + 15) / 16 * 16);
   const size_t lds = sizeof(double) * (want_k ? m.max_range_values : m.max_range_rows) + g.inc_cap +
-                     (size_t)m.tune.waves * (krec ? wave_buf_bytes<Rule, R, true>() : wave_buf_bytes<Rule, R, false>()) +
+                     (size_t)m.tune.waves * (krec ? (sym ? wave_buf_bytes<Rule, R, true, sizeof(R) == 8>()
+                                                         : wave_buf_bytes<Rule, R, true>())
+                                                  : wave_buf_bytes<Rule, R, false>()) +
                      (mt.row_off_u ? upper_table_bytes(m) : 0);
   const dim3 grid((unsigned)m.n_ranges), blk(64 * m.tune.waves);
-#define TLFEA_GATHER(F, K, A, KR)                                                \
-  do {                                                                           \
-    if (int rc = allow_lds(k_gather<Rule, R, F, K, A, KR>, lds)) return rc;      \
-    hipLaunchKernelGGL((k_gather<Rule, R, F, K, A, KR>), grid, blk, lds, s, g); \
+#define TLFEA_GATHER_S(F, K, A, KR, SY)                                              \
+  do {                                                                               \
+    if (int rc = allow_lds(k_gather<Rule, R, F, K, A, KR, SY>, lds)) return rc;      \
+    hipLaunchKernelGGL((k_gather<Rule, R, F, K, A, KR, SY>), grid, blk, lds, s, g); \
+  } while (0)
+#define TLFEA_GATHER(F, K, A, KR)                                                            \
+  do {                                                                                       \
+    if (KR && sym) TLFEA_GATHER_S(F, K, A, KR, (KR && sizeof(R) == 8)); else TLFEA_GATHER_S(F, K, A, KR, false); \
   } while (0)
   if (want_k && want_f) {
     if (accum) TLFEA_GATHER(true, true, true, true); else TLFEA_GATHER(true, true, false, true);
@@ -1718,6 +1754,7 @@ int launch_nodes_rule(const Mesh& m, const void* stage, double* f, double* vals,
     if (accum) TLFEA_GATHER(true, false, true, false); else TLFEA_GATHER(true, false, false, false);
   }
 #undef TLFEA_GATHER
+#undef TLFEA_GATHER_S
   TLFEA_HIP_CHECK(hipGetLastError());
   return TLFEA_OK;
 }
@@ -1885,6 +1922,12 @@ bool use_rows(const Mesh& m, bool want_k) {
     return !(v && v[0] == '0');
   }();
   return on && want_k && m.precision == TLFEA_MIXED && m.d_incpos && (m.elem_type != TLFEA_T10 || m.d_rank_inc);
+}
+
+// The float64 point records of a tangent pass take the symmetric layout for
+// undamped materials (64 values instead of 96).
+bool point_records_sym(const Mesh& m, bool want_k) {
+  return want_k && m.precision == TLFEA_FP64 && sym_records(m);
 }
 
 bool use_force_blocks(const Mesh& m, bool want_k) {

@@ -501,6 +501,7 @@ static int run_points(tlfea_mesh_t mesh, const double* q, const double* qdot, do
   rc = tlfea::launch_points(m, a, want_k, s);
   m.staged = rc ? 0 : (want_k ? (tlfea::use_rows(m, true) ? 3 : 2) : (tlfea::use_force_blocks(m, false) ? 4 : 1));
   m.staged_precision = m.precision;
+  m.staged_sym = m.staged == 2 && tlfea::point_records_sym(m, true);
   return rc;
 }
 

@@ -177,6 +177,7 @@ struct Mesh {
                                   // 3 element row blocks, 4 element force blocks
                                   // records, 3 element row blocks (force + tangent)
   int staged_precision = -1;
+  bool staged_sym = false;        // point records of the last pass 1 in the symmetric float64 layout
 
   bool has_pattern = false;
   int64_t nnz = -1;
@@ -305,6 +306,7 @@ MatParams make_params(int material, const double* params, double eta, double lam
 // for T10 only).  Pass 1 then leaves one row block per incidence instead of
 // per-point records.
 bool use_rows(const Mesh& m, bool want_k);
+bool point_records_sym(const Mesh& m, bool want_k);
 // Force-only path (every element type; TLFEA_FORCE_BLOCKS=0 switches it off):
 // pass 1 leaves one float-or-double force block of 3 mc values per incidence.
 bool use_force_blocks(const Mesh& m, bool want_k);

@@ -1340,8 +1340,8 @@ __device__ __forceinline__ void rows_mc_mfma_contract(const AsmArgs& a, const in
 }
 
 template <class Rule, bool SYM, bool MF>
-__global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc(AsmArgs a, const int32_t* __restrict__ incpos,
-                                                                 float* __restrict__ rows) {
+__device__ __forceinline__ void elem_rows_mc_tile(const AsmArgs& a, const int32_t* __restrict__ incpos,
+                                                  float* __restrict__ rows, int64_t blk) {
   constexpr int NQ = Rule::NQ, NEN = Rule::NEN, NPN = Rule::NPN, EB = rows_mc_elems<Rule>();
   constexpr int BLK = rows_mc_block<NEN>();
   constexpr int RS = SYM ? kRecS : kRecL;  // LDS record stride (symmetric layout for undamped materials)
@@ -1350,7 +1350,7 @@ __global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc(AsmArgs a, cons
   __shared__ __align__(16) unsigned char smem[NOD > REC ? NOD : REC];
   __shared__ float dn[NQ * NEN * 3];  // unit-scaled parent gradients, dN_a(q)_m at 3 (NEN q + a) + m
   const int tid = threadIdx.x;
-  const int64_t e0 = (int64_t)blockIdx.x * EB;
+  const int64_t e0 = blk * EB;
   const int ne = (int)(a.n_elem - e0 < EB ? a.n_elem - e0 : EB);
   double* nod = reinterpret_cast<double*>(smem);
   gather_nodal<Rule>(a, e0, ne, nod);
@@ -1449,6 +1449,28 @@ __global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc(AsmArgs a, cons
   }
 }
 
+template <class Rule, bool SYM, bool MF>
+__global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc(AsmArgs a, const int32_t* __restrict__ incpos,
+                                                                 float* __restrict__ rows) {
+  elem_rows_mc_tile<Rule, SYM, MF>(a, incpos, rows, blockIdx.x);
+}
+
+// many bodies: every body starts on a workgroup of its own, found by bisection;
+// the full tangent layout (the bodies' materials may differ)
+template <class Rule, bool MF>
+__global__ __launch_bounds__(kRowsMcThreads) void k_elem_rows_mc_batch(BatchArgs b) {
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = b.n_bodies - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.bodies[mid].rblock_off <= blk) lo = mid; else hi = mid - 1;
+  }
+  const BatchBody& B = b.bodies[lo];
+  const AsmArgs a = body_args(b, B, lo);
+  elem_rows_mc_tile<Rule, false, MF>(a, B.incpos, (float*)b.stage + B.blk_inc_off * rows_mc_block<Rule::NEN>(),
+                                     blk - B.rblock_off);
+}
+
 // Pass 2 over the ANCF row blocks: a lane per (incidence, row r, component k)
 // loads its NEN entries (16-byte pieces) and its element's rank row (4 bytes,
 // element order), and adds them into the range's LDS segment at
@@ -1520,6 +1542,26 @@ __global__ __launch_bounds__(512) void k_gather_rows_mc(GatherArgs g) {
   __shared__ int32_t rowo[kMaxRangeNodes * 12];
   const int r = remap_tile(blockIdx.x, gridDim.x);
   gather_rows_mc<Rule, WANT_F, WANT_K, ACCUM>(g, g.ranges[r], g.ranges[r + 1], smem, pre, rowo);
+}
+
+template <class Rule>
+__global__ __launch_bounds__(512) void k_gather_rows_mc_batch(BatchArgs b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t pre[kMaxRangeNodes + 1];
+  __shared__ int32_t rowo[kMaxRangeNodes * 12];
+  const int r = remap_tile(blockIdx.x, gridDim.x);
+  const BatchRange br = b.ranges[r];
+  const BatchBody& B = b.bodies[br.body];
+  GatherArgs g{};
+  g.inc_off = B.inc_off;
+  g.inc = B.inc;
+  g.row_off = B.row_off;
+  g.rank = B.rank;
+  g.stage = (const float*)b.stage + B.blk_inc_off * rows_mc_block<Rule::NEN>();
+  g.f = b.f + B.dof_off;
+  g.vals = b.vals + B.nnz_off;
+  g.inc_cap = b.inc_cap;
+  gather_rows_mc<Rule, true, true, false>(g, br.I0, br.I1, smem, pre, rowo);
 }
 
 // ---------------------------------------------------------------------------
@@ -1949,6 +1991,17 @@ size_t stage_bytes(const Mesh& m, bool want_k) {
 size_t row_block_bytes() { return kRowBlk * sizeof(float); }
 int row_elems() { return kRowElems; }
 
+size_t row_block_bytes_for(int elem_type, int gl0) {
+  if (elem_type == TLFEA_T10) return row_block_bytes();
+  if (elem_type == TLFEA_ANCF3243) return rows_mc_block<RuleBeam::NEN>() * sizeof(float);
+  return rows_mc_block<16>() * sizeof(float);
+}
+int row_elems_for(int elem_type, int gl0) {
+  if (elem_type == TLFEA_T10) return kRowElems;
+  if (elem_type == TLFEA_ANCF3243) return rows_mc_elems<RuleBeam>();
+  return gl0 == 3 ? rows_mc_elems<RuleAncf<3, 3, 2>>() : rows_mc_elems<RuleAncf<4, 4, 3>>();
+}
+
 size_t stage_record_bytes(int precision) {
   return (size_t)kRecK * (precision == TLFEA_MIXED ? sizeof(float) : sizeof(double));
 }
@@ -2101,6 +2154,25 @@ int launch_block_sum(const Mesh& m, const double* blk, double* out, hipStream_t 
   return TLFEA_OK;
 }
 
+template <class Rule>
+int launch_rows_mc_batch(const GatherTuning& tu, const BatchArgs& b, int n_ranges, size_t lds, hipStream_t s) {
+  constexpr bool MF = Rule::NEN == 16;  // the shell's slot tiles on the matrix cores
+  if (b.n_rblocks > 0) {
+    if (mc_mfma())
+      hipLaunchKernelGGL((k_elem_rows_mc_batch<Rule, MF>), dim3((unsigned)b.n_rblocks), dim3(kRowsMcThreads), 0, s,
+                         b);
+    else
+      hipLaunchKernelGGL((k_elem_rows_mc_batch<Rule, false>), dim3((unsigned)b.n_rblocks), dim3(kRowsMcThreads), 0,
+                         s, b);
+  }
+  TLFEA_HIP_CHECK(hipGetLastError());
+  const size_t lds_all = lds + b.inc_cap;
+  if (int rc = allow_lds(k_gather_rows_mc_batch<Rule>, lds_all)) return rc;
+  hipLaunchKernelGGL(k_gather_rows_mc_batch<Rule>, dim3(n_ranges), dim3(64 * tu.waves), lds_all, s, b);
+  TLFEA_HIP_CHECK(hipGetLastError());
+  return TLFEA_OK;
+}
+
 int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tu, const BatchArgs& b,
                  int n_ranges, size_t lds, hipStream_t s, const BatchSchedule& sc) {
   if (n_ranges == 0) return TLFEA_OK;
@@ -2121,6 +2193,11 @@ int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tu, 
                        sc.range_order, n_ranges, sc.counters + 1);
     TLFEA_HIP_CHECK(hipGetLastError());
     return TLFEA_OK;
+  }
+  if (b.rows && elem_type != TLFEA_T10) {
+    if (elem_type == TLFEA_ANCF3243) return launch_rows_mc_batch<RuleBeam>(tu, b, n_ranges, lds, s);
+    if (gl0 == 3) return launch_rows_mc_batch<RuleAncf<3, 3, 2>>(tu, b, n_ranges, lds, s);
+    return launch_rows_mc_batch<RuleAncf<4, 4, 3>>(tu, b, n_ranges, lds, s);
   }
   if (b.rows) {
     if (b.n_rblocks > 0)

@@ -32,7 +32,7 @@ struct tlfea_batch_s {
   size_t ranges_cap = 0;             // BatchRange entries d_ranges holds
   tlfea::GatherTuning tune;          // pass-2 launch shape the ranges are cut for
   int64_t n_points = 0, n_blocks = 0;
-  int rows = 0;                      // element-row path (T10, mixed)
+  int rows = 0;                      // element-row path (mixed; persistent schedule for T10)
   int64_t n_inc = 0, n_rblocks = 0;  // its row blocks and pass-1 workgroups
   size_t lds = 0;
   int inc_cap = 0;
@@ -94,7 +94,7 @@ static int upload(T*& d, size_t& cap, const std::vector<T>& h) {
 // last; the ranges by decreasing work (incidences, then rows); grids of as
 // many workgroups as the GPU holds at once.
 static int batch_plan_lpt(tlfea_batch_s* b, int tile_elems) {
-  if (!b->rows) return TLFEA_ERR_UNSUPPORTED;
+  if (!b->rows || b->elem_type != TLFEA_T10) return TLFEA_ERR_UNSUPPORTED;
   if (tile_elems != 16 && tile_elems != tlfea::row_elems()) return TLFEA_ERR_INVALID;
   struct Tile {
     int64_t work, body_size;
@@ -244,7 +244,7 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
   b->precision = m0.precision;
   b->rows = 1;
   for (int i = 0; i < n_bodies; ++i)
-    b->rows &= (meshes[i]->m.elem_type == TLFEA_T10 && tlfea::use_rows(meshes[i]->m, true)) ? 1 : 0;
+    b->rows &= tlfea::use_rows(meshes[i]->m, true) ? 1 : 0;
   std::vector<BatchBody> bodies(n_bodies);
   b->dof_off.assign(n_bodies + 1, 0);
   b->nnz_off.assign(n_bodies + 1, 0);
@@ -280,9 +280,11 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
     b->n_points += m.n_elem * m.n_qp;
     b->n_blocks += (m.n_elem * m.n_qp + tlfea::kStageThreads - 1) / tlfea::kStageThreads;
     b->n_inc += m.n_elem * m.n_pn;
-    b->n_rblocks += (m.n_elem + tlfea::row_elems() - 1) / tlfea::row_elems();
+    const int reb = tlfea::row_elems_for(b->elem_type, b->gl0);
+    b->n_rblocks += (m.n_elem + reb - 1) / reb;
     // pass 2 addresses a body's row blocks in 16-byte units with 32-bit offsets
-    if (b->rows && m.n_elem * m.n_pn * (int64_t)(tlfea::row_block_bytes() / 16) >= ((int64_t)1 << 32)) {
+    if (b->rows && b->elem_type == TLFEA_T10 &&
+        m.n_elem * m.n_pn * (int64_t)(tlfea::row_block_bytes() / 16) >= ((int64_t)1 << 32)) {
       delete b;
       return TLFEA_ERR_TOO_LARGE;
     }
@@ -295,7 +297,7 @@ TLFEA_API int tlfea_batch_create(const tlfea_mesh_t* meshes, int32_t n_bodies, t
     b->generation.push_back(m.generation);
   }
   if (b->n_blocks > INT32_MAX || b->n_rblocks > INT32_MAX) { delete b; return TLFEA_ERR_TOO_LARGE; }
-  const size_t stage = b->rows ? (size_t)b->n_inc * tlfea::row_block_bytes()
+  const size_t stage = b->rows ? (size_t)b->n_inc * tlfea::row_block_bytes_for(b->elem_type, b->gl0)
                                : (size_t)b->n_points * tlfea::stage_record_bytes(b->precision);
   if (hipSetDevice(b->device) != hipSuccess) { delete b; return TLFEA_ERR_HIP; }
   if (hipMalloc(&b->d_bodies, sizeof(BatchBody) * bodies.size()) != hipSuccess ||
@@ -453,7 +455,7 @@ TLFEA_API int tlfea_batch_get_gather_shape(tlfea_batch_t b, tlfea_gather_shape* 
 TLFEA_API int tlfea_batch_set_schedule(tlfea_batch_t b, int32_t persistent, int32_t tile_elems) {
   if (!b || (persistent != 0 && persistent != 1)) return TLFEA_ERR_INVALID;
   if (!batch_current(b)) return TLFEA_ERR_INVALID;
-  if (persistent && !b->rows) return TLFEA_ERR_UNSUPPORTED;
+  if (persistent && !(b->rows && b->elem_type == TLFEA_T10)) return TLFEA_ERR_UNSUPPORTED;
   if (hipSetDevice(b->device) != hipSuccess) return TLFEA_ERR_HIP;
   return batch_set_schedule(b, persistent, tile_elems);
 }
@@ -463,7 +465,7 @@ TLFEA_API int tlfea_batch_get_schedule(tlfea_batch_t b, int32_t* persistent, int
   if (!b) return TLFEA_ERR_INVALID;
   const tlfea::BatchSchedule& sc = b->sched;
   if (persistent) *persistent = sc.persistent;
-  if (tile_elems) *tile_elems = sc.persistent ? sc.tile_elems : tlfea::row_elems();
+  if (tile_elems) *tile_elems = sc.persistent ? sc.tile_elems : tlfea::row_elems_for(b->elem_type, b->gl0);
   if (grid_tiles) *grid_tiles = sc.persistent ? sc.grid_tiles : (int32_t)b->n_rblocks;
   if (grid_ranges) *grid_ranges = sc.persistent ? sc.grid_ranges : b->n_ranges;
   return TLFEA_OK;
@@ -482,7 +484,7 @@ TLFEA_API int tlfea_batch_autotune(tlfea_batch_t b, const double* d_q, const dou
     int persistent, tile_elems;
   };
   std::vector<Cand> cands{{0, tlfea::row_elems()}};
-  if (b->rows) {
+  if (b->rows && b->elem_type == TLFEA_T10) {
     cands.push_back({1, tlfea::row_elems()});
     cands.push_back({1, 16});
   }

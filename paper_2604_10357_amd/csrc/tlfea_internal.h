@@ -314,6 +314,8 @@ size_t stage_bytes(const Mesh& m, bool want_k);
 size_t stage_record_bytes(int precision);
 size_t row_block_bytes();  // element-row path: bytes per (element, node) row block
 int row_elems();           // element-row path: elements per pass-1 workgroup
+size_t row_block_bytes_for(int elem_type, int gl0);  // the same per element type
+int row_elems_for(int elem_type, int gl0);
 int launch_batch(int elem_type, int gl0, int precision, const GatherTuning& tune, const BatchArgs& b,
                  int n_ranges, size_t lds, hipStream_t s, const BatchSchedule& sc);
 

@@ -447,8 +447,9 @@ int tlfea_batch_assemble_loop(tlfea_batch_t batch, const double* d_q, const doub
  * tiles of the largest bodies first and partial tiles last, then node ranges
  * by decreasing work (longest-processing-time order).  Either schedule gives
  * the same results up to rounding order.  TLFEA_ERR_UNSUPPORTED for a batch
- * off the T10 element-row path (ANCF and float64 batches run per item).  get: grid_tiles / grid_ranges receive the
- * workgroups launched per pass (any pointer may be NULL). */
+ * off the T10 element-row path (ANCF and float64 batches run per item).
+ * get: grid_tiles / grid_ranges receive the workgroups launched per pass (any
+ * pointer may be NULL). */
 int tlfea_batch_set_schedule(tlfea_batch_t batch, int32_t persistent, int32_t tile_elems);
 int tlfea_batch_get_schedule(tlfea_batch_t batch, int32_t* persistent, int32_t* tile_elems, int32_t* grid_tiles,
                              int32_t* grid_ranges);

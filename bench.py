@@ -429,6 +429,8 @@ def bench_mesh(args, torch, wl, wname):
                           "elements_per_s": bo["value"], "achieved_GBs": bo["roofline"]["achieved"],
                           "frac": bo["roofline"]["frac"], "algorithmic_bytes": bo["roofline"]["algorithmic_bytes"],
                           "kernel": bo["roofline"]["kernel"], "tuning": bo["tuning"]}
+        if "fp64" in bo:
+            out["batched"]["fp64"] = bo["fp64"]
         print(f"[bench] batched: graph {bo['ms_per_step']:.3f} ms, loop {bo['per_body_loop']['ms_per_step']:.3f} ms",
               file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
@@ -486,6 +488,30 @@ def bench_batched(args, torch):
             b.assemble(q, qd, hs, f, vals, loop=True)
         ms_loop = time_calls(lambda: b.assemble(q, qd, hs, f, vals, loop=True), args.steps, torch)
     s.synchronize()
+    fp64 = None
+    if args.precision == "mixed":
+        # the plain FP64 form of the same batch, and the mixed result against it
+        f_mx, v_mx = f.cpu().numpy(), vals.cpu().numpy()
+        meshes64 = []
+        for wl in wls:
+            m = TLMesh(wl.mesh, wl.material, "fp64")
+            m.build_pattern()
+            meshes64.append(m)
+        b64 = TLBatch(meshes64)
+        with torch.cuda.stream(s):
+            for _ in range(args.warmup):
+                b64.assemble(q, qd, hs, f, vals)
+            ms64 = time_calls(lambda: b64.assemble(q, qd, hs, f, vals), args.steps, torch)
+            b64.assemble(q, qd, hs, f, vals)
+        s.synchronize()
+        f64, v64 = f.cpu().numpy(), vals.cpu().numpy()
+        fp64 = {"ms_per_step": ms64, "value": n_el / (ms64 * 1e-3), "speedup_mixed_over_fp64": ms64 / ms,
+                "mixed_vs_fp64": {"f": float(np.abs(f_mx - f64).max() / np.abs(f64).max()),
+                                  "K": float(np.abs(v_mx - v64).max() / np.abs(v64).max())},
+                "kernel": "k_stage_batch + k_gather_batch (one graph)"}
+        b64.close()
+        for m in meshes64:
+            m.close()
     achieved = B / (ms * 1e-3) / 1e9
     out = {
         "metric": "f_int+K assembly elements/s and HBM GB/s; mixed vs FP64 at stated error",
@@ -505,6 +531,8 @@ def bench_batched(args, torch):
         "per_body_loop": {"ms_per_step": ms_loop, "value": n_el / (ms_loop * 1e-3),
                           "speedup_batched_over_loop": ms_loop / ms},
     }
+    if fp64 is not None:
+        out["fp64"] = fp64
     b.close()
     for m in meshes:
         m.close()

@@ -318,7 +318,10 @@ def bench_mesh(args, torch, wl, wname):
                      "algorithmic_bytes_layout": B_layout,
                      "frac_layout": B_layout / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         # the same call against the vector arithmetic roofline (contraction FLOPs only)
-        "valu": {"flop_per_element": contraction_flop(wl),
+        # the shell's mixed contraction runs on the matrix cores (FP32 MFMA, the same 157.3 peak)
+        "valu": {"units": ("matrix cores (fp32 MFMA 16x16x4)" if kname == "ANCF3443" and rows_path
+                           else "vector ALUs"),
+                 "flop_per_element": contraction_flop(wl),
                  "achieved_TFLOPs": contraction_flop(wl) * n_el / (ms * 1e-3) / 1e12,
                  "peak_TFLOPs": FP32_PEAK_TFLOPS if args.precision == "mixed" else FP64_PEAK_TFLOPS,
                  "frac": contraction_flop(wl) * n_el / (ms * 1e-3) / 1e12

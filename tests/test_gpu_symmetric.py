@@ -12,6 +12,7 @@ Mooney-Rivlin), both shell rules (the matrix-core contraction) and the beam,
 in both precisions, for f, K and the upper-triangle output."""
 import numpy as np
 import pytest
+import torch
 
 from paper_2604_10357_amd import workloads as W
 from tests.gpu_util import cuda, make_mesh, rel_err
@@ -72,3 +73,22 @@ def test_symmetric_path_matches_full_path(name, wl, precision):
     n = len(ro) - 1
     keep = np.concatenate([np.arange(ro[r], ro[r + 1])[cols[ro[r]:ro[r + 1]] >= r] for r in range(n)])
     assert rel_err(kus, kf[keep])[0] <= GATE[precision]
+
+
+@pytest.mark.parametrize("name,wl", [CASES[0], CASES[2]], ids=[CASES[0][0], CASES[2][0]])
+def test_split_pass_keeps_the_layout_of_its_pass_1(name, wl):
+    """Pass 2 alone reduces what pass 1 left, in the layout pass 1 wrote it: a
+    material change between the two (here to a damped one, whose pass 1 would
+    write the full float64 records) does not change how pass 2 reads them."""
+    print(f"[gpu] split pass layout {name}", flush=True)
+    m = make_mesh(wl, "fp64")
+    q, qd = cuda(wl.q), cuda(wl.qdot)
+    f, vals = m.assemble(q, qd, alpha=1e-3, beta=1.0)
+    m.assemble_points(q, qd, 1e-3, 1.0, want_tangent=True)
+    mat = wl.material
+    m.set_material(W.Material(mat.kind, mat.params, 1e3, 1e3))
+    f2, v2 = torch.empty_like(f), torch.empty_like(vals)
+    m.assemble_nodes(f2, v2)
+    assert rel_err(f2.cpu().numpy(), f.cpu().numpy())[0] <= 1e-14
+    assert rel_err(v2.cpu().numpy(), vals.cpu().numpy())[0] <= 1e-14
+    m.close()

@@ -274,7 +274,9 @@ int tlfea_assemble_nodes(tlfea_mesh_t mesh, double* d_f, double* d_vals, int32_t
  *   d_gparam = d(w . f)/d(p0, p1, p2, kv_eta, kv_lambda)  (5 float64; may be NULL);
  *              p = (E, nu, -) for SVK, (mu10, mu01, kappa) for Mooney-Rivlin.
  * The transpose of Eq. tangent_block (Sec. 4.4.2) applied to w, in float64
- * whatever the mesh precision.  Outputs are overwritten.  Needs the CSR
+ * whatever the mesh precision.  Outputs are overwritten; only the products
+ * asked for are formed (d_gqdot == NULL leaves out the velocity adjoint and its
+ * work), and repeated calls give the same bits.  Needs the CSR
  * pattern (TLFEA_ERR_NO_PATTERN otherwise: its node ranges drive the per-node
  * sums); uses the mesh's work buffer, so a following tlfea_assemble_nodes
  * without a new tlfea_assemble_points returns TLFEA_ERR_INVALID. */

@@ -1599,7 +1599,7 @@ __global__ __launch_bounds__(kForceThreads) void k_elem_force(AsmArgs a, const i
   const int pl = act ? tid : 0;  // idle lanes evaluate point 0 and store nothing
   const int el = pl / NQ, q = pl - el * NQ;
   double Jinv[9], det, Hd[9], Fd[9];
-  tile_kinematics<Rule, (NEN > 8)>(a, nod + 6 * NEN * el, e0 + el, q, Jinv, det, Hd, Fd);
+  tile_kinematics<Rule, true>(a, nod + 6 * NEN * el, e0 + el, q, Jinv, det, Hd, Fd);
   __syncthreads();  // the nodal values are consumed: the LDS holds Phat from here on
   PointOut<R> o;
   const MatParams mp = launch_material(a);

@@ -122,9 +122,10 @@ __device__ __forceinline__ void gather_nodal(const AsmArgs& a, int64_t e_lo, int
 // PART: coefficients in steps of TLFEA_KIN_UNROLL instead of all at once (a
 // full unroll keeps every table load in flight; for the shell's 16
 // coefficients that caps the kernels at one wave per SIMD).  Measured per
-// kernel: steps for the shell everywhere and for the T10 force kernel, a full
-// unroll for the T10 element rows and the beam.
-template <class Rule, bool PART = (Rule::NEN > 10)>
+// kernel: steps for the four-coefficient elements (shell and beam) everywhere
+// and for the T10 force and backward kernels, a full unroll for the T10
+// element rows and point records.
+template <class Rule, bool PART = (Rule::MC == 4 || Rule::NEN > 10)>
 __device__ __forceinline__ void tile_kinematics(const AsmArgs& a, const double* ne, int64_t e, int q,
                                                 double (&Jinv)[9], double& det, double (&Hd)[9], double (&Fd)[9]) {
   constexpr int NEN = Rule::NEN;

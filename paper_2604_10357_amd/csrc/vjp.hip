@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_elem(AsmArgs a, const doubl
   const int pl = act ? tid : 0;  // idle lanes evaluate point 0 and store nothing
   const int el = pl / NQ, q = pl - el * NQ;
   double Jinv[9], det, Hd[9], Fd[9], Wg[9];
-  tile_kinematics<Rule, (NEN > 8)>(a, nod + 6 * NEN * el, e0 + el, q, Jinv, det, Hd, Fd);
+  tile_kinematics<Rule, true>(a, nod + 6 * NEN * el, e0 + el, q, Jinv, det, Hd, Fd);
   {
     // W = sum_a w_a (x) g_a, the first position coefficient's value taken out
     // of every position coefficient (the position gradients sum to zero)
